@@ -1,0 +1,408 @@
+"""FP64 CPU oracle of the sputtered-atom transport and of the composition map.
+
+TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no code
+with the HIP path (``paper_2411_14413_amd``) and imports nothing from it; both
+read the plain input objects of ``sputter_inputs``.
+
+The transport itself is plain C in ``spx_oracle.c`` (double precision, one
+particle history after another, following the Methods section of the paper,
+"The SIMTRA model").  This module marshals inputs for it (ctypes + numpy) and
+holds the post-processing steps in numpy/torch-CPU float64:
+
+* normalisation of integer tallies to a deposition profile per launched atom;
+* the 342 measurement areas and the area average of a profile;
+* the composition map: arrival fraction weighted by sputter rate, then by bulk
+  density over atomic mass, to at.% (Methods, the calculation paragraph, and the
+  Introduction on the linear power-rate relation);
+* the squared Euclidean distance d_e^2 of compositions (Results, d_e equation);
+* the least-squares power-rate line (Supporting Information, Table S1).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from functools import lru_cache
+from typing import Dict, List, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+SEG_LEN = 48
+P_LEN = 8
+REC = 8
+STATE_DEPOSITED, STATE_WALL, STATE_ESCAPED = 1, 2, 3
+COUNTER_NAMES = ("launched", "deposited", "wall", "escaped", "collisions", "diffusive_steps")
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(LIB_PATH)
+        L.or_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.or_u01.argtypes = [ctypes.c_uint32]
+        L.or_u01.restype = ctypes.c_double
+        L.or_norm_cdf.argtypes = [ctypes.c_double]
+        L.or_norm_cdf.restype = ctypes.c_double
+        L.or_norm_inv.argtypes = [ctypes.c_double]
+        L.or_norm_inv.restype = ctypes.c_double
+        L.or_moliere.argtypes = [ctypes.c_double]
+        L.or_moliere.restype = ctypes.c_double
+        L.or_gauss_legendre01.argtypes = [ctypes.c_int, _dp, _dp]
+        L.or_closest_approach.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
+        L.or_closest_approach.restype = ctypes.c_double
+        L.or_theta_cm.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+        L.or_theta_cm.restype = ctypes.c_double
+        L.or_beta_max.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int]
+        L.or_beta_max.restype = ctypes.c_double
+        L.or_build_table.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_double, ctypes.c_double, _dp, _dp]
+        L.or_run.argtypes = [_dp, ctypes.c_int, _dp, _dp, _dp, ctypes.c_uint64, ctypes.c_uint64,
+                             ctypes.c_uint64, ctypes.c_int, _u64p, _u64p, _dp]
+        L.or_run.restype = ctypes.c_int
+        L.or_run_list.argtypes = [_dp, ctypes.c_int, _dp, _dp, _dp, ctypes.c_uint64, _u32p, _u32p,
+                                  ctypes.c_int64, ctypes.c_int, _dp]
+        L.or_seg_info.argtypes = [_dp, _dp, _dp, _dp, _dp]
+        L.or_launch.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_uint64, ctypes.c_uint32, _dp]
+        L.or_launch_batch.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, _dp]
+        L.or_flights.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64,
+                                 ctypes.c_double, _dp]
+        L.or_lambda_m.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_double]
+        L.or_lambda_m.restype = ctypes.c_double
+        L.or_table_theta.argtypes = [_dp, _dp, _dp, ctypes.c_double, ctypes.c_double]
+        L.or_table_theta.restype = ctypes.c_double
+        L.or_collide.argtypes = [_dp, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double, _dp]
+        L.or_gas_velocity.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp]
+        L.or_hit.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_double, _dp]
+        L.or_walk.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _dp]
+        L.or_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+# ---------------------------------------------------------------------------
+# Random numbers and the normal distribution
+# ---------------------------------------------------------------------------
+def philox(ctr, key) -> np.ndarray:
+    """Philox4x32-10 blocks for an [n, 4] array of counters and one 2-word key."""
+    ctr = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(-1, 4))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32).reshape(2))
+    out = np.empty_like(ctr)
+    L = lib()
+    for i in range(ctr.shape[0]):
+        L.or_philox4x32_10(_p(ctr[i], _u32p), _p(k, _u32p), _p(out[i], _u32p))
+    return out
+
+
+def u01(x: int) -> float:
+    return lib().or_u01(int(x))
+
+
+def norm_inv(p: float) -> float:
+    return lib().or_norm_inv(float(p))
+
+
+def norm_cdf(z: float) -> float:
+    return lib().or_norm_cdf(float(z))
+
+
+# ---------------------------------------------------------------------------
+# Scattering integral and table
+# ---------------------------------------------------------------------------
+MOLIERE, COULOMB, INVERSE_SQUARE = 0, 1, 2
+
+
+def theta_cm(eps: float, beta: float, kind: int = MOLIERE, nq: int = 128) -> float:
+    return lib().or_theta_cm(kind, float(eps), float(beta), nq)
+
+
+def closest_approach(eps: float, beta: float, kind: int = MOLIERE) -> float:
+    return lib().or_closest_approach(kind, float(eps), float(beta))
+
+
+def beta_max(eps: float, theta_min: float = 0.1, kind: int = MOLIERE, nq: int = 128) -> float:
+    return lib().or_beta_max(kind, float(eps), float(theta_min), nq)
+
+
+def gauss_legendre01(n: int):
+    t = np.empty(n)
+    w = np.empty(n)
+    lib().or_gauss_legendre01(n, _p(t), _p(w))
+    return t, w
+
+
+def params_array(params) -> np.ndarray:
+    return np.array([params.theta_min, params.E_th_kT, float(params.event_cap), float(params.table_ne),
+                     float(params.table_ns), params.log_eps_lo, params.log_eps_hi, 0.0], dtype=np.float64)
+
+
+@lru_cache(maxsize=8)
+def _table_cached(theta_min, ne, ns, lo, hi, kind):
+    theta = np.empty(ne * ns)
+    bmax = np.empty(ne)
+    lib().or_build_table(kind, theta_min, ne, ns, lo, hi, _p(theta), _p(bmax))
+    theta.setflags(write=False)
+    bmax.setflags(write=False)
+    return theta, bmax
+
+
+def table(params, kind: int = MOLIERE):
+    """(theta [ne*ns], beta_max [ne]) in FP64, built by the oracle's own quadrature."""
+    return _table_cached(float(params.theta_min), int(params.table_ne), int(params.table_ns),
+                         float(params.log_eps_lo), float(params.log_eps_hi), kind)
+
+
+# ---------------------------------------------------------------------------
+# Inputs -> flat segment records (one per (config, cathode))
+# ---------------------------------------------------------------------------
+def segments(cfgs: Sequence) -> np.ndarray:
+    rows = []
+    off = 0
+    for c, cfg in enumerate(cfgs):
+        ch, g = cfg.chamber, cfg.grid
+        for k, cat in enumerate(cfg.cathodes):
+            r = np.zeros(SEG_LEN)
+            r[0], r[1] = c, k
+            r[2:10] = [ch.radius, ch.z_lo, ch.z_hi, ch.pressure, ch.T, ch.gas_mass, ch.gas_Z, ch.gas_motion]
+            r[10:13], r[13:16], r[16:19] = g.center, g.normal, g.u_axis
+            r[19:24] = [g.half_u, g.half_v, g.shape, g.nu, g.nv]
+            r[24:27], r[27:30], r[30:33] = cat.center, cat.normal, cat.u_axis
+            r[33:38] = [cat.radius, cat.rt_mu, cat.rt_sigma, cat.rt_lo, cat.rt_hi]
+            r[38:43] = [cat.U_s, cat.E_i, cat.k_cut, cat.mass, cat.Z]
+            r[43] = cat.n_particles
+            r[44] = off
+            off += g.nu * g.nv
+            rows.append(r)
+    return np.ascontiguousarray(np.stack(rows))
+
+
+def _args(cfgs, params):
+    S = segments(cfgs)
+    prm = params_array(params)
+    th, bm = table(params)
+    return S, prm, th, bm
+
+
+def seg_info(cfgs, params, seg: int = 0) -> Dict[str, float]:
+    S, prm, th, bm = _args(cfgs, params)
+    out = np.empty(15)
+    lib().or_seg_info(_p(S[seg]), _p(prm), _p(th), _p(bm), _p(out))
+    names = ("Lambda", "E_max", "s_max", "a_mm", "eps_per_eV", "n_mm3", "kT", "E_th", "lam_th",
+             "PhiA", "QB", "dPhi", "mu_red", "vth", "vg")
+    return dict(zip(names, out.tolist()))
+
+
+def launch(cfgs, params, seed: int, pid: int, seg: int = 0):
+    S, prm, th, bm = _args(cfgs, params)
+    out = np.empty(7)
+    lib().or_launch(_p(S[seg]), _p(prm), _p(th), _p(bm), seed, pid, _p(out))
+    return out[:3].copy(), out[3:6].copy(), float(out[6])
+
+
+def launch_batch(cfgs, params, seed: int, pid0: int, n: int, seg: int = 0) -> np.ndarray:
+    """[n, 7] launch samples (x, d, E) of particles pid0 .. pid0+n-1."""
+    S, prm, th, bm = _args(cfgs, params)
+    out = np.empty((n, 7))
+    lib().or_launch_batch(_p(S[seg]), _p(prm), _p(th), _p(bm), seed, pid0, n, _p(out))
+    return out
+
+
+def flights(cfgs, params, seed: int, pid0: int, n: int, E: float, seg: int = 0) -> np.ndarray:
+    """First-flight lengths at fixed energy E for n particles."""
+    S, prm, th, bm = _args(cfgs, params)
+    out = np.empty(n)
+    lib().or_flights(_p(S[seg]), _p(prm), _p(th), _p(bm), seed, pid0, n, float(E), _p(out))
+    return out
+
+
+def lambda_m(cfgs, params, E: float, seg: int = 0) -> float:
+    S, prm, th, bm = _args(cfgs, params)
+    return lib().or_lambda_m(_p(S[seg]), _p(prm), _p(th), _p(bm), float(E))
+
+
+def table_theta(params, eps: float, s: float) -> float:
+    prm = params_array(params)
+    th, bm = table(params)
+    return lib().or_table_theta(_p(prm), _p(th), _p(bm), float(eps), float(s))
+
+
+def collide(cfgs, params, E: float, d, V, u_b: float, u_phi: float, seg: int = 0):
+    S, prm, th, bm = _args(cfgs, params)
+    io = np.array([E, d[0], d[1], d[2]], dtype=np.float64)
+    Vv = np.ascontiguousarray(np.asarray(V, dtype=np.float64))
+    lib().or_collide(_p(S[seg]), _p(prm), _p(th), _p(bm), _p(Vv), float(u_b), float(u_phi), _p(io))
+    return float(io[0]), io[1:].copy()
+
+
+def gas_velocity(cfgs, params, w, seg: int = 0) -> np.ndarray:
+    S, prm, th, bm = _args(cfgs, params)
+    ww = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+    V = np.empty(3)
+    lib().or_gas_velocity(_p(S[seg]), _p(prm), _p(th), _p(bm), _p(ww), _p(V))
+    return V
+
+
+def hit(cfgs, params, x, d, ell: float = math.inf, seg: int = 0):
+    S, prm, th, bm = _args(cfgs, params)
+    xx = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    dd = np.ascontiguousarray(np.asarray(d, dtype=np.float64))
+    out = np.empty(3)
+    lib().or_hit(_p(S[seg]), _p(prm), _p(th), _p(bm), _p(xx), _p(dd), float(ell), _p(out))
+    return float(out[0]), int(out[1]), int(out[2])
+
+
+def walk(cfgs, params, seed: int, pid: int, n_steps: int, seg: int = 0) -> np.ndarray:
+    S, prm, th, bm = _args(cfgs, params)
+    out = np.empty(3)
+    lib().or_walk(_p(S[seg]), _p(prm), _p(th), _p(bm), seed, pid, n_steps, _p(out))
+    return out
+
+
+def max_threads() -> int:
+    return lib().or_max_threads()
+
+
+def run(cfgs, params, seed: int, pid_begin: int = 0, pid_end: int = None, n_threads: int = 0,
+        records: bool = False) -> Dict[str, object]:
+    """Simulate particles [pid_begin, pid_end) of every (config, cathode).
+
+    Returns ``counts`` (list of [nv, nu] uint64 arrays, one per segment),
+    ``counters`` ([n_seg, 6] uint64, order COUNTER_NAMES), ``records``
+    ([n, 8] float64: x, y, z, state, bin, events, diffusive steps, final E) and
+    ``threads`` (OpenMP threads used)."""
+    S, prm, th, bm = _args(cfgs, params)
+    n_seg = S.shape[0]
+    shapes = [(cfg.grid.nv, cfg.grid.nu) for cfg in cfgs for _ in cfg.cathodes]
+    n_bins = sum(a * b for a, b in shapes)
+    if pid_end is None:
+        pid_end = 1 << 62
+    counts = np.zeros(n_bins, dtype=np.uint64)
+    counters = np.zeros((n_seg, 6), dtype=np.uint64)
+    n_rec = sum(max(0, min(int(S[k, 43]), pid_end) - pid_begin) for k in range(n_seg))
+    rec = np.zeros((n_rec, REC)) if records else None
+    used = lib().or_run(_p(S), n_seg, _p(prm), _p(th), _p(bm), seed, pid_begin, pid_end, n_threads,
+                        _p(counts, _u64p), _p(counters, _u64p), _p(rec) if records else None)
+    out_counts = []
+    off = 0
+    for (nv, nu) in shapes:
+        out_counts.append(counts[off:off + nv * nu].reshape(nv, nu))
+        off += nv * nu
+    return dict(counts=out_counts, counters=counters, records=rec, threads=used)
+
+
+def run_list(cfgs, params, seed: int, seg_ids, pids, n_threads: int = 0) -> np.ndarray:
+    """Records ([n, 8]) of an explicit list of (segment, particle index) pairs."""
+    S, prm, th, bm = _args(cfgs, params)
+    sid = np.ascontiguousarray(np.asarray(seg_ids, dtype=np.uint32))
+    pid = np.ascontiguousarray(np.asarray(pids, dtype=np.uint32))
+    rec = np.zeros((sid.size, REC))
+    lib().or_run_list(_p(S), S.shape[0], _p(prm), _p(th), _p(bm), seed, _p(sid, _u32p), _p(pid, _u32p),
+                      sid.size, n_threads, _p(rec))
+    return rec
+
+
+# ---------------------------------------------------------------------------
+# Post-processing (float64)
+# ---------------------------------------------------------------------------
+def normalize(counts: np.ndarray, n_launched: int, grid) -> np.ndarray:
+    """Deposition profile per launched atom and mm^2: count / (N * bin area)."""
+    area = (2.0 * grid.half_u / grid.nu) * (2.0 * grid.half_v / grid.nv)
+    return np.asarray(counts, dtype=np.float64) / (float(n_launched) * area)
+
+
+def area_centres(n_areas: int = 342, pitch: float = 4.5) -> np.ndarray:
+    """Measurement-area centres: lattice points (pitch*i, pitch*j) nearest the wafer
+    centre, ties in distance broken by polar angle ascending in [0, 2 pi)."""
+    m = int(math.ceil(math.sqrt(n_areas))) + 2
+    pts = []
+    for i in range(-m, m + 1):
+        for j in range(-m, m + 1):
+            ang = math.atan2(j, i)
+            if ang < 0.0:
+                ang += 2.0 * math.pi
+            pts.append((i * i + j * j, ang, i, j))
+    pts.sort()
+    sel = pts[:n_areas]
+    return np.array([[pitch * p[2], pitch * p[3]] for p in sel], dtype=np.float64)
+
+
+def area_gather(profile: np.ndarray, grid, centres: np.ndarray, half_width: float = 2.25) -> np.ndarray:
+    """Area value = mean of the profile over the square of half-width ``half_width``
+    around each centre, each bin weighted by its overlap with the square."""
+    nv, nu = profile.shape
+    du = 2.0 * grid.half_u / nu
+    dv = 2.0 * grid.half_v / nv
+    ue = -grid.half_u + du * np.arange(nu + 1)
+    ve = -grid.half_v + dv * np.arange(nv + 1)
+    out = np.empty(len(centres))
+    for a, (cu, cv) in enumerate(centres):
+        ou = np.clip(np.minimum(ue[1:], cu + half_width) - np.maximum(ue[:-1], cu - half_width), 0.0, None)
+        ov = np.clip(np.minimum(ve[1:], cv + half_width) - np.maximum(ve[:-1], cv - half_width), 0.0, None)
+        w = np.outer(ov, ou)
+        out[a] = float((w * profile).sum() / w.sum())
+    return out
+
+
+def composition(f, a, b, P, M, rho, fref=None):
+    """at.% per (batch, area, cathode).
+
+    f [K, J]: arrival fraction per launched atom at each area; P [B, K] powers;
+    a, b [K]: sputter rate = a P + b at the calibration point; M [K] atomic masses;
+    rho [K] bulk densities; fref [K] the profile value at the calibration point
+    (default: mean over the areas).  Atoms of element k at area j are proportional
+    to rate_k * f_k(j)/fref_k * rho_k / M_k; at.% is 100 times their share.
+    Works on numpy arrays and on float64 torch tensors (for the autograd reference).
+    """
+    try:
+        import torch
+        is_t = isinstance(f, torch.Tensor)
+    except ImportError:  # pragma: no cover
+        is_t = False
+    if fref is None:
+        fref = f.mean(axis=1) if not is_t else f.mean(dim=1)
+    w = (a[None, :] * P + b[None, :]) * (rho / (M * fref))[None, :]          # [B, K]
+    y = w[:, None, :] * (f.T)[None, :, :]                                      # [B, J, K]
+    S = y.sum(axis=2, keepdims=True) if not is_t else y.sum(dim=2, keepdim=True)
+    return 100.0 * y / S
+
+
+def sq_euclid(c, c_target):
+    """Sum over areas and elements of (c - c*)^2, per batch element: d_e^2 summed over areas."""
+    d = c - c_target
+    return (d * d).sum(axis=(1, 2)) if isinstance(d, np.ndarray) else (d * d).sum(dim=(1, 2))
+
+
+def composition_grads(f, a, b, P, M, rho, fref, c_target, grad_scale=None):
+    """Reference gradient of sum_b sum_j sum_k (c - c*)^2 by float64 torch autograd on the CPU."""
+    import torch
+    T = lambda x: torch.tensor(np.asarray(x, dtype=np.float64), requires_grad=True)
+    tf, ta, tb, tP, tM, tr, tfr = (T(v) for v in (f, a, b, P, M, rho, fref))
+    c = composition(tf, ta, tb, tP, tM, tr, tfr)
+    loss = sq_euclid(c, torch.tensor(np.asarray(c_target, dtype=np.float64))).sum()
+    loss.backward()
+    g = lambda t: t.grad.detach().numpy().copy()
+    return dict(c=c.detach().numpy(), loss=float(loss.detach()), f=g(tf), a=g(ta), b=g(tb), P=g(tP), M=g(tM),
+                rho=g(tr), fref=g(tfr))
+
+
+def fit_power_rate(P, r):
+    """Least-squares line rate = a P + b through (P_i, r_i)."""
+    A = np.stack([np.asarray(P, dtype=np.float64), np.ones(len(P))], axis=1)
+    sol, *_ = np.linalg.lstsq(A, np.asarray(r, dtype=np.float64), rcond=None)
+    return float(sol[0]), float(sol[1])

@@ -1,0 +1,252 @@
+"""Pins of the oracle's transport loop: geometry, conservation, zero-pressure profile.
+
+* surface intersection against a brute-force march along the ray (signed
+  distances of each surface, bisection at the first sign change);
+* particle conservation: deposited + wall + escaped = launched, per (config, cathode);
+* at 0 Pa the deposition profile is the analytic line-of-sight flux of a cosine
+  emitter: a ring of radius a at height h under a parallel plate gives
+  q(rho) = (h^2/pi) A / (A^2 - B^2)^(3/2), A = h^2 + rho^2 + a^2, B = 2 a rho, averaged
+  over the racetrack radius and integrated over each bin (per-bin z-scores, chi^2);
+* a split run (particle ranges) sums to the full run exactly (counter-based RNG);
+* records agree with the tallies; the event cap turns long histories into ESCAPED.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+import sputter_inputs as si
+
+
+# ---------------------------------------------------------------------------
+# brute-force ray march
+# ---------------------------------------------------------------------------
+def _first_crossing(f, t_max, h=0.05):
+    t0, f0 = 1e-9, f(1e-9)
+    t = t0
+    while t < t_max:
+        t1 = min(t + h, t_max)
+        f1 = f(t1)
+        if (f0 > 0) != (f1 > 0):
+            a, b = t, t1
+            for _ in range(80):
+                m = 0.5 * (a + b)
+                if (f(m) > 0) == (f0 > 0):
+                    a = m
+                else:
+                    b = m
+            return 0.5 * (a + b)
+        t, f0 = t1, f1
+    return math.inf
+
+
+def _brute_hit(cfg, x, d):
+    g, cat, ch = cfg.grid, cfg.cathodes[0], cfg.chamber
+    x, d = np.asarray(x), np.asarray(d)
+    gn, gu = np.array(g.normal), np.array(g.u_axis)
+    gv = np.cross(gn, gu)
+    cands = []
+    ts = _first_crossing(lambda t: (x + t * d - g.center) @ gn, 1000.0)
+    if ts < math.inf:
+        q = x + ts * d - g.center
+        ins = (abs(q @ gu) <= g.half_u and abs(q @ gv) <= g.half_v) if g.shape == 0 else \
+            ((q @ gu) ** 2 + (q @ gv) ** 2 <= g.half_u**2)
+        if ins:
+            cands.append((ts, 1 if d @ gn < 0 else 2))
+    cn, cu = np.array(cat.normal), np.array(cat.u_axis)
+    cv = np.cross(cn, cu)
+    tc = _first_crossing(lambda t: (x + t * d - cat.center) @ cn, 1000.0)
+    if tc < math.inf:
+        q = x + tc * d - cat.center
+        if (q @ cu) ** 2 + (q @ cv) ** 2 <= cat.radius**2:
+            cands.append((tc, 2))
+    tw = _first_crossing(lambda t: max(math.hypot(*(x + t * d)[:2]) - ch.radius,
+                                       ch.z_lo - (x + t * d)[2], (x + t * d)[2] - ch.z_hi), 2000.0)
+    cands.append((tw, 2))
+    return min(cands, key=lambda c: c[0])
+
+
+@pytest.mark.parametrize("which", ["single", "quat"])
+def test_hit_test_against_ray_march(which, params):
+    cfg = si.single_ni(0.5, 10) if which == "single" else si.quaternary(counts=[10] * 4)
+    rng = np.random.default_rng(17)
+    n_dep = 0
+    for trial in range(150):
+        while True:
+            x = np.array([rng.uniform(-190, 190), rng.uniform(-190, 190), rng.uniform(5, 295)])
+            if math.hypot(x[0], x[1]) < 195:
+                break
+        if trial % 3 == 0:           # aim at the substrate to exercise deposition
+            tgt = np.array(cfg.grid.center) + rng.uniform(-45, 45, 3) * np.array([1, 1, 0])
+            d = tgt - x
+        else:
+            d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        t, state, b = oracle.hit([cfg], params, x, d)
+        tb, sb = _brute_hit(cfg, x, d)
+        assert abs(t - tb) < 1e-6, (x, d, t, tb)
+        assert state == sb
+        if state == 1:
+            n_dep += 1
+            g = cfg.grid
+            q = x + t * d - np.array(g.center)
+            gu = np.array(g.u_axis)
+            gv = np.cross(np.array(g.normal), gu)
+            du, dv = 2 * g.half_u / g.nu, 2 * g.half_v / g.nv
+            iu, iv = b % g.nu, b // g.nu
+            assert -g.half_u + iu * du - 1e-9 <= q @ gu <= -g.half_u + (iu + 1) * du + 1e-9
+            assert -g.half_v + iv * dv - 1e-9 <= q @ gv <= -g.half_v + (iv + 1) * dv + 1e-9
+        # a finite flight shorter than the hit leaves the particle in the gas
+        t2, s2, _ = oracle.hit([cfg], params, x, d, ell=0.5 * t)
+        assert s2 == 0
+    assert n_dep > 10
+
+
+def test_launch_does_not_hit_own_cathode(params):
+    cfg = si.single_ni(0.0, 10)
+    s = oracle.launch_batch([cfg], params, seed=0, pid0=0, n=200)
+    for row in s:
+        t, state, _ = oracle.hit([cfg], params, row[:3], row[3:6])
+        assert t > 1.0 and state in (1, 2)
+
+
+# ---------------------------------------------------------------------------
+# analytic zero-pressure profile of the single-target geometry
+# ---------------------------------------------------------------------------
+def analytic_bin_fractions(cfg, n_a=96, n_xy=4):
+    """Expected deposited fraction per bin [nv, nu] for a cosine emitter whose start
+    radius is the truncated normal of the cathode, under a parallel substrate."""
+    cat, g = cfg.cathodes[0], cfg.grid
+    h = abs(g.center[2] - cat.center[2])
+    tn = stats.truncnorm((cat.rt_lo - cat.rt_mu) / cat.rt_sigma, (cat.rt_hi - cat.rt_mu) / cat.rt_sigma,
+                         loc=cat.rt_mu, scale=cat.rt_sigma)
+    xa, wa = np.polynomial.legendre.leggauss(n_a)
+    a = cat.rt_lo + (cat.rt_hi - cat.rt_lo) * 0.5 * (xa + 1)
+    wa = wa * 0.5 * (cat.rt_hi - cat.rt_lo) * tn.pdf(a)
+    assert abs(wa.sum() - 1.0) < 1e-6
+    xq, wq = np.polynomial.legendre.leggauss(n_xy)
+    du, dv = 2 * g.half_u / g.nu, 2 * g.half_v / g.nv
+    uc = -g.half_u + du * (np.arange(g.nu) + 0.5)
+    vc = -g.half_v + dv * (np.arange(g.nv) + 0.5)
+    out = np.zeros((g.nv, g.nu))
+    for i, (ox, wx) in enumerate(zip(xq, wq)):
+        for j, (oy, wy) in enumerate(zip(xq, wq)):
+            U = uc[None, :] + 0.5 * du * ox
+            Vv = vc[:, None] + 0.5 * dv * oy
+            rho2 = U**2 + Vv**2
+            A = h * h + rho2[..., None] + a**2
+            B2 = 4 * a**2 * rho2[..., None]
+            q = (h * h / math.pi) * A / (A * A - B2) ** 1.5
+            out += wx * wy * 0.25 * du * dv * (q * wa).sum(axis=-1)
+    return out
+
+
+def test_analytic_total_fraction():
+    frac = analytic_bin_fractions(si.single_ni(0.0, 1)).sum()
+    assert abs(frac - 0.23316386) < 2e-7
+    # a point source on the axis gives the textbook view factor of a square: cross-check
+    cfg = si.single_ni(0.0, 1)
+    cfg.cathodes[0].rt_mu, cfg.cathodes[0].rt_sigma = 1e-6, 1e-5
+    cfg.cathodes[0].rt_lo, cfg.cathodes[0].rt_hi = 0.0, 2e-6
+    # textbook view factor, differential area to a parallel rectangle with a corner
+    # above it: F = [X/sqrt(1+X^2) atan(Y/sqrt(1+X^2)) + Y/sqrt(1+Y^2) atan(X/sqrt(1+Y^2))]/(2 pi)
+    X = Y = 50.0 / 100.0
+    f_corner = (X / math.sqrt(1 + X * X) * math.atan(Y / math.sqrt(1 + X * X)) +
+                Y / math.sqrt(1 + Y * Y) * math.atan(X / math.sqrt(1 + Y * Y))) / (2 * math.pi)
+    assert abs(analytic_bin_fractions(cfg, n_a=8).sum() - 4 * f_corner) < 2e-6
+
+
+def test_zero_pressure_profile_matches_line_of_sight(params):
+    n = 1_000_000
+    cfg = si.single_ni(0.0, n)
+    r = oracle.run([cfg], params, seed=0)
+    counts = r["counts"][0].astype(np.float64)
+    exp = n * analytic_bin_fractions(cfg)
+    z = (counts - exp) / np.sqrt(exp)
+    chi2 = float((z**2).sum())
+    dof = counts.size
+    assert chi2 < dof + 4.5 * math.sqrt(2 * dof), chi2
+    assert np.abs(z).max() < 5.0
+    tot = counts.sum()
+    assert abs(tot - exp.sum()) < 4.5 * math.sqrt(exp.sum())
+    c = r["counters"][0]
+    assert c[0] == n and c[1] + c[2] + c[3] == n and c[3] == 0 and c[4] == 0 and c[5] == 0
+
+
+# ---------------------------------------------------------------------------
+# conservation, determinism, records, event cap
+# ---------------------------------------------------------------------------
+def test_conservation_and_split_run(params):
+    cfgs = [si.single_ni(0.5, 3000), si.single_ni(2.0, 500), si.quaternary(0.7, 20, 120, [800, 300, 500, 400])]
+    full = oracle.run(cfgs, params, seed=42, records=True)
+    C = full["counters"]
+    assert np.array_equal(C[:, 0], C[:, 1] + C[:, 2] + C[:, 3])
+    assert np.array_equal(C[:, 0], [3000, 500, 800, 300, 500, 400])
+    a = oracle.run(cfgs, params, seed=42, pid_begin=0, pid_end=250)
+    b = oracle.run(cfgs, params, seed=42, pid_begin=250)
+    for k in range(len(full["counts"])):
+        assert np.array_equal(full["counts"][k], a["counts"][k] + b["counts"][k])
+    assert np.array_equal(C, a["counters"] + b["counters"])
+    # records reproduce the tallies exactly
+    rec = full["records"]
+    off = 0
+    for k, N in enumerate(C[:, 0]):
+        rk = rec[off:off + int(N)]
+        off += int(N)
+        dep = rk[rk[:, 3] == 1]
+        h = np.bincount(dep[:, 4].astype(np.int64), minlength=full["counts"][k].size)
+        assert np.array_equal(h.reshape(full["counts"][k].shape), full["counts"][k])
+        assert int((rk[:, 3] == 2).sum()) == C[k, 2]
+        assert int(rk[:, 6].sum()) == C[k, 5]
+    # the same particles through run_list give the same records
+    seg_ids = np.repeat(np.arange(6), C[:, 0].astype(np.int64))
+    pids = np.concatenate([np.arange(int(N)) for N in C[:, 0]])
+    sel = np.random.default_rng(0).choice(len(pids), 300, replace=False)
+    rl = oracle.run_list(cfgs, params, 42, seg_ids[sel], pids[sel])
+    assert np.array_equal(rl, rec[sel])
+    # another seed gives another history
+    other = oracle.run(cfgs, params, seed=43)
+    assert not all(np.array_equal(x, y) for x, y in zip(other["counts"], full["counts"]))
+
+
+def test_deposits_lie_on_the_substrate(params):
+    cfg = si.quaternary(0.5, 25, 150, [2000, 500, 1000, 800])
+    r = oracle.run([cfg], params, seed=1, records=True)
+    rec = r["records"]
+    dep = rec[rec[:, 3] == 1]
+    assert len(dep) > 100
+    assert np.abs(dep[:, 2] - si.WAFER_Z).max() < 1e-9
+    assert (np.hypot(dep[:, 0], dep[:, 1]) <= 50 + 1e-9).all()
+    wall = rec[rec[:, 3] == 2]
+    # every wall end point is on some absorbing surface: chamber, cathode disc or wafer back
+    on_chamber = (np.abs(np.hypot(wall[:, 0], wall[:, 1]) - 200) < 1e-6) | (np.abs(wall[:, 2]) < 1e-6) | \
+                 (np.abs(wall[:, 2] - 300) < 1e-6)
+    on_wafer = np.abs(wall[:, 2] - si.WAFER_Z) < 1e-9
+    on_cat = np.zeros(len(wall), dtype=bool)
+    for c in cfg.cathodes:
+        on_cat |= np.abs((wall[:, :3] - c.center) @ np.array(c.normal)) < 1e-6
+    assert (on_chamber | on_wafer | on_cat).all()
+
+
+def test_event_cap_escapes(params):
+    p = si.Params(event_cap=4)
+    cfg = si.single_ni(2.0, 2000)
+    r = oracle.run([cfg], p, seed=0, records=True)
+    C = r["counters"][0]
+    assert C[3] > 0 and C[0] == C[1] + C[2] + C[3]
+    esc = r["records"][r["records"][:, 3] == 3]
+    assert np.all(esc[:, 5] == 4)
+    assert r["records"][:, 5].max() <= 4
+
+
+def test_pressure_changes_transport(params):
+    # more gas: more collisions per particle, thermalised atoms walk, fewer reach the substrate
+    res = {}
+    for p in (0.0, 0.5, 2.0):
+        r = oracle.run([si.single_ni(p, 4000)], params, seed=5)
+        res[p] = r["counters"][0]
+    assert res[0.0][4] == 0 and res[0.5][4] > 0 and res[2.0][4] > res[0.5][4]
+    assert res[2.0][5] / 4000 > res[0.5][5] / 4000 > 0
+    assert res[0.0][1] > res[0.5][1] > res[2.0][1]
