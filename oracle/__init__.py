@@ -52,6 +52,7 @@ def lib():
             _b.build()
         L = ctypes.CDLL(LIB_PATH)
         L.or_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
+        L.or_philox_batch.argtypes = [_u32p, ctypes.c_int64, _u32p, _u32p]
         L.or_u01.argtypes = [ctypes.c_uint32]
         L.or_u01.restype = ctypes.c_double
         L.or_norm_cdf.argtypes = [ctypes.c_double]
@@ -85,7 +86,7 @@ def lib():
         L.or_table_theta.restype = ctypes.c_double
         L.or_collide.argtypes = [_dp, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_double, _dp]
         L.or_gas_velocity.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp]
-        L.or_hit.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_double, _dp]
+        L.or_hit.argtypes = [_dp, _dp, _dp, _dp, _dp, _dp, ctypes.c_double, ctypes.c_int, _dp]
         L.or_walk.argtypes = [_dp, _dp, _dp, _dp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, _dp]
         L.or_max_threads.restype = ctypes.c_int
         _lib = L
@@ -107,6 +108,15 @@ def philox(ctr, key) -> np.ndarray:
     L = lib()
     for i in range(ctr.shape[0]):
         L.or_philox4x32_10(_p(ctr[i], _u32p), _p(k, _u32p), _p(out[i], _u32p))
+    return out
+
+
+def philox_batch(ctr, key) -> np.ndarray:
+    """Same as philox() for large counter arrays (one C call)."""
+    ctr = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(-1, 4))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32).reshape(2))
+    out = np.empty_like(ctr)
+    lib().or_philox_batch(_p(ctr, _u32p), ctr.shape[0], _p(k, _u32p), _p(out, _u32p))
     return out
 
 
@@ -258,12 +268,12 @@ def gas_velocity(cfgs, params, w, seg: int = 0) -> np.ndarray:
     return V
 
 
-def hit(cfgs, params, x, d, ell: float = math.inf, seg: int = 0):
+def hit(cfgs, params, x, d, ell: float = math.inf, seg: int = 0, first_flight: bool = False):
     S, prm, th, bm = _args(cfgs, params)
     xx = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
     dd = np.ascontiguousarray(np.asarray(d, dtype=np.float64))
     out = np.empty(3)
-    lib().or_hit(_p(S[seg]), _p(prm), _p(th), _p(bm), _p(xx), _p(dd), float(ell), _p(out))
+    lib().or_hit(_p(S[seg]), _p(prm), _p(th), _p(bm), _p(xx), _p(dd), float(ell), int(first_flight), _p(out))
     return float(out[0]), int(out[1]), int(out[2])
 
 

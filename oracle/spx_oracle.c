@@ -73,6 +73,12 @@ void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* Many blocks at once: out[4i..4i+3] = philox(ctr[4i..4i+3], key). */
+void or_philox_batch(const uint32_t* ctr, int64_t n, const uint32_t key[2], uint32_t* out)
+{
+    for (int64_t i = 0; i < n; ++i) or_philox4x32_10(ctr + 4 * i, key, out + 4 * i);
+}
+
 /* RN on ]0,1]: 24 random bits, shifted up by one ulp of 2^-24 so 0 is excluded and 1 is reachable. */
 double or_u01(uint32_t x) { return (double)((x >> 8) + 1u) * (1.0 / 16777216.0); }
 
@@ -483,7 +489,7 @@ static void launch(const seg_t* s, uint64_t seed, uint32_t pid, double x[3], dou
 /* ------------------------------------------------------------------------- */
 typedef struct { double t; int state; int bin; } hit_t;
 
-static hit_t hit_test(const seg_t* s, const double x[3], const double d[3], double ell)
+static hit_t hit_test(const seg_t* s, const double x[3], const double d[3], double ell, int first_flight)
 {
     hit_t best = {INFINITY, OR_ALIVE, -1};
     /* substrate plate */
@@ -517,8 +523,11 @@ static hit_t hit_test(const seg_t* s, const double x[3], const double d[3], doub
             }
         }
     }
-    /* emitting cathode disc, absorbing on both faces */
-    {
+    /* emitting cathode disc, absorbing on both faces.  The first flight starts on the
+     * target plane (the atom leaves the surface into the gas), and a straight line meets
+     * a plane once, so the target cannot be hit at t > 0 on that flight: it is not tested,
+     * rather than left to the rounding of a distance that is zero. */
+    if (!first_flight) {
         const double dn = dot(d, s->cat_n);
         if (dn != 0.0) {
             double w[3] = {s->cat_c[0] - x[0], s->cat_c[1] - x[1], s->cat_c[2] - x[2]};
@@ -650,7 +659,7 @@ static void trace(const seg_t* s, const tab_t* tb, uint64_t seed, uint32_t pid, 
         } else {
             diffusive_draw(s, u, d, &ell);
         }
-        hit_t h = hit_test(s, x, d, ell);
+        hit_t h = hit_test(s, x, d, ell, e == 1);
         if (h.state != OR_ALIVE) {
             for (int i = 0; i < 3; ++i) x[i] += h.t * d[i];
             res->state = h.state;
@@ -867,13 +876,13 @@ void or_gas_velocity(const double* seg, const double* prm, const double* theta, 
 
 /* Hit test: out = {t, state, bin}. */
 void or_hit(const double* seg, const double* prm, const double* theta, const double* betamax,
-            const double* x, const double* d, double ell, double* out)
+            const double* x, const double* d, double ell, int first_flight, double* out)
 {
     tab_t tb;
     make_tab(prm, theta, betamax, &tb);
     seg_t s;
     seg_init(seg, prm, &tb, &s);
-    hit_t h = hit_test(&s, x, d, ell);
+    hit_t h = hit_test(&s, x, d, ell, first_flight);
     out[0] = h.t; out[1] = h.state; out[2] = h.bin;
 }
 

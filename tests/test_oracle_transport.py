@@ -108,8 +108,23 @@ def test_launch_does_not_hit_own_cathode(params):
     cfg = si.single_ni(0.0, 10)
     s = oracle.launch_batch([cfg], params, seed=0, pid0=0, n=200)
     for row in s:
-        t, state, _ = oracle.hit([cfg], params, row[:3], row[3:6])
+        t, state, _ = oracle.hit([cfg], params, row[:3], row[3:6], first_flight=True)
         assert t > 1.0 and state in (1, 2)
+
+
+@pytest.mark.parametrize("tilt", [0.0, 25.0, 37.0])
+def test_first_flight_leaves_tilted_targets(tilt, params):
+    # in vacuum every history is one straight flight from the target surface: it must
+    # end far from its start point (no absorption by the emitting target at t ~ 0)
+    n = 4000
+    cfg = si.quaternary(0.0, tilt, 150.0, [n] * 4)
+    r = oracle.run([cfg], params, seed=2, records=True)
+    rec = r["records"]
+    for k in range(4):
+        start = oracle.launch_batch([cfg], params, seed=2, pid0=0, n=n, seg=k)[:, :3]
+        end = rec[k * n:(k + 1) * n, :3]
+        assert np.linalg.norm(end - start, axis=1).min() > 1.0
+        assert np.all(rec[k * n:(k + 1) * n, 5] == 1)
 
 
 # ---------------------------------------------------------------------------
