@@ -1,0 +1,230 @@
+/*
+ * spx.h -- C-ABI of libspx: Monte Carlo transport of sputtered atoms on MI355X (gfx950).
+ *
+ * The method is the one of Thelen et al., "A Python-Based Approach to Sputter
+ * Deposition Simulations in Combinatorial Materials Science" (arXiv 2411.14413):
+ * Methods, "The SIMTRA model" (launch from the racetrack with a Thompson energy
+ * and a cosine emission law, exponential free flights, surface intersection and
+ * deposition on collecting "dummy" objects, elastic collisions with the gas), the
+ * calculation paragraph that closes Methods (Moliere-screened Coulomb potential,
+ * gas motion, diffusion of thermalised atoms, arrival fractions converted to at.%
+ * with sputter rates, bulk densities and atomic masses), and the Euclidean
+ * distance d_e of compositions (Results).  A multi-cathode system is split into
+ * independent single-cathode runs, one per (configuration, cathode) "segment"
+ * (Methods, "The SIMTRA Python wrapper"); all segments of a plan run in one launch.
+ *
+ * Conventions
+ *   Units: mm, eV, u (atomic mass unit), K, Pa.  Host structs are double precision.
+ *   Pointers named d_* are device pointers (HBM of the current HIP device); h_* are
+ *   host pointers.  The caller owns every buffer it passes; the library owns the
+ *   plan and what the plan allocates.  `stream` is a hipStream_t (NULL = default).
+ *   Every function returns SPX_OK (0) or a negative SPX_E* code; on error the
+ *   outputs are unspecified and spx_last_error() describes the failure.  No C++
+ *   exception crosses this boundary.  Work is enqueued on `stream`; device-side
+ *   faults surface at the next synchronising call.  A plan is not thread-safe.
+ *
+ * Random numbers: Philox4x32-10, counter (particle, event, (config << 8) | cathode,
+ * sub-block), key (seed low word, seed high word); a 32-bit word x gives
+ * u = ((x >> 8) + 1) * 2^-24 in ]0,1] (the paper's RN_1 range).  Results are a
+ * function of (configs, params, seed) only: integer tallies are bit-identical
+ * whatever the launch shape.
+ */
+#ifndef SPX_H
+#define SPX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SPX_OK 0
+#define SPX_EINVAL (-1)   /* invalid argument or configuration */
+#define SPX_ENOMEM (-2)   /* device or host allocation failed */
+#define SPX_EDEVICE (-3)  /* HIP runtime error, or no usable gfx950 device */
+#define SPX_ESTATE (-4)   /* call not valid in the plan's current state */
+
+/* Terminal states of a particle (spx_record.state). */
+#define SPX_DEPOSITED 1   /* front face of the substrate, inside the plate: tallied */
+#define SPX_WALL 2        /* chamber, cathode disc, or substrate back face */
+#define SPX_ESCAPED 3     /* event cap reached or non-finite state */
+
+/* Counters per segment, in this order (spx_run d_counters[seg * SPX_N_COUNTERS + i]). */
+#define SPX_C_LAUNCHED 0
+#define SPX_C_DEPOSITED 1
+#define SPX_C_WALL 2
+#define SPX_C_ESCAPED 3
+#define SPX_C_COLLISIONS 4      /* ballistic flights that ended in a gas collision */
+#define SPX_C_DIFFUSIVE 5       /* diffusive steps that ended in the gas */
+#define SPX_N_COUNTERS 6
+
+/* Magnetron cathode: planar circular target (Methods, "The SIMTRA Python wrapper": the
+ * magnetron object holds the element, the racetrack and the geometry). */
+typedef struct spx_cathode {
+    double center[3];      /* target centre, mm */
+    double normal[3];      /* unit normal pointing into the gas */
+    double u_axis[3];      /* unit in-plane axis; v = normal x u_axis */
+    double radius;         /* target radius, mm; the disc absorbs on both faces */
+    double rt_mu, rt_sigma;/* racetrack start radius ~ normal(rt_mu, rt_sigma) ... */
+    double rt_lo, rt_hi;   /* ... truncated to [rt_lo, rt_hi], azimuth uniform */
+    double U_s;            /* surface binding energy, eV (Thompson distribution) */
+    double E_i;            /* incident ion energy, eV */
+    double k_cut;          /* E_max = k_cut * Lambda * E_i - U_s, Lambda = 4 M_i M_t/(M_i+M_t)^2,
+                              M_i = gas mass (the working-gas ion) */
+    double mass;           /* sputtered atom mass, u */
+    int32_t Z;             /* sputtered atom number */
+    int32_t reserved0;
+    double cos_coeff[6];   /* emission law sum c_i cos^i; only {0,1,0,0,0,0} (cosine) is accepted */
+    uint64_t n_particles;  /* particles launched from this cathode, < 2^32 */
+} spx_cathode;
+
+/* Vacuum chamber: absorbing cylinder on the z axis with a homogeneous gas in thermal
+ * equilibrium (Methods, "The SIMTRA model"). */
+typedef struct spx_chamber {
+    double radius, z_lo, z_hi;   /* mm */
+    double pressure;             /* Pa; 0 = vacuum (straight flights) */
+    double T;                    /* K */
+    double gas_mass;             /* u */
+    int32_t gas_Z;
+    int32_t gas_motion;          /* 1: thermal velocity of the collision partner is sampled */
+} spx_chamber;
+
+/* Collecting substrate ("dummy" object) carrying the tally grid. */
+typedef struct spx_grid {
+    double center[3];
+    double normal[3];            /* faces the cathodes; hits from the other side are WALL */
+    double u_axis[3];            /* v = normal x u_axis */
+    double half_u, half_v;       /* rectangle half-sizes, mm; disc radius = half_u */
+    int32_t shape;               /* 0 rectangle, 1 disc (then half_v == half_u) */
+    int32_t nu, nv;              /* bins, row-major [iv][iu]; nu * nv <= 2^24 */
+    int32_t reserved0;
+} spx_grid;
+
+typedef struct spx_config {
+    spx_chamber chamber;
+    spx_grid grid;
+    int32_t n_cathodes;          /* 1 .. 255 */
+    int32_t reserved0;
+    const spx_cathode* cathodes; /* host array of n_cathodes; deep-copied by spx_plan_create */
+} spx_config;
+
+typedef struct spx_params {
+    double theta_min;            /* rad; CM deflection at the cross-section cut-off (0.1) */
+    double E_th_kT;              /* thermalisation threshold in units of k_B T (3) */
+    uint32_t event_cap;          /* flights per particle before ESCAPED (2^20) */
+    int32_t table_ne, table_ns;  /* scattering-table nodes in log10(eps) and b/b_max (256, 257) */
+    int32_t precision;           /* 32: batched FP32 transport; 64: plain FP64 per-segment comparator */
+    double log_eps_lo, log_eps_hi; /* table range of log10(eps) (-10, 0) */
+} spx_params;
+
+/* Per-particle terminal record (optional output of spx_run), segment-major:
+ * index = first particle index of the segment + particle index. */
+typedef struct spx_record {
+    double x, y, z;              /* end point (chamber frame, mm) */
+    double E;                    /* energy at the end, eV (last ballistic value if thermalised) */
+    uint32_t state;              /* SPX_DEPOSITED / SPX_WALL / SPX_ESCAPED */
+    uint32_t bin;                /* iv * nu + iu if DEPOSITED, else 0xFFFFFFFF */
+    uint32_t events;             /* flights taken */
+    uint32_t diffusive;          /* diffusive steps that ended in the gas */
+} spx_record;
+
+typedef struct spx_plan spx_plan;
+
+/* Validate and deep-copy `n_cfgs` configurations; derive per-segment constants in
+ * double precision; build the scattering table with an FP64 kernel on the current
+ * device (Moliere potential, Firsov screening length; theta_cm(log10 eps, b/b_max)
+ * and b_max(eps) where theta_cm = theta_min), synchronously.  Rejects: pressure < 0,
+ * T <= 0, zero cathodes, all cathodes with n_particles == 0, n_particles >= 2^32,
+ * a cathode or substrate outside the chamber, nu*nv > 2^24 or < 1, rt_lo >= rt_hi,
+ * E_max <= 0, masses <= 0, a non-cosine emission law, non-unit or non-orthogonal
+ * axes, more than 2^24 configurations.  *out is set only on success. */
+int spx_plan_create(const spx_config* h_cfgs, int32_t n_cfgs, const spx_params* h_params, spx_plan** out);
+
+/* Sizes of spx_run's outputs: total tally bins over all segments, counters
+ * (n_segments * SPX_N_COUNTERS), total particles, segments.  Any pointer may be NULL. */
+int spx_plan_query(const spx_plan* plan, uint64_t* n_bins_total, uint64_t* n_counters,
+                   uint64_t* n_particles_total, int32_t* n_segments);
+
+/* Offsets of each segment in the outputs: h_bin_off[seg] (into d_counts/d_profiles)
+ * and h_first[seg] (into d_records), arrays of n_segments entries each (nullable). */
+int spx_plan_layout(const spx_plan* plan, uint64_t* h_bin_off, uint64_t* h_first);
+
+/* Run every particle of every segment with the given seed.
+ *   d_counts    uint64[n_bins_total]  deposits per bin (overwritten)
+ *   d_counters  uint64[n_counters]    SPX_C_* per segment (overwritten)
+ *   d_profiles  double[n_bins_total]  counts / (N_seg * bin area), mm^-2 per launched atom; nullable
+ *   d_records   spx_record[n_particles_total]; nullable
+ * precision 32 runs the whole plan as one persistent launch (replayed from a HIP
+ * graph); precision 64 runs one plain FP64 launch per segment.  Asynchronous. */
+int spx_run(spx_plan* plan, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters,
+            double* d_profiles, spx_record* d_records, void* stream);
+
+/* Choose launch parameters of the FP32 transport (block size, waves per CU, refill
+ * threshold) by timing short runs on `stream`; synchronous; tallies are unaffected. */
+int spx_autotune(spx_plan* plan, void* stream);
+
+/* Current FP32-transport launch parameters: blocks, threads per block, refill threshold. */
+int spx_get_launch(const spx_plan* plan, int32_t* blocks, int32_t* threads, int32_t* refill_min);
+/* Override them (blocks <= 0: fill the device at the occupancy limit). */
+int spx_set_launch(spx_plan* plan, int32_t blocks, int32_t threads, int32_t refill_min);
+
+/* Copy the FP64 scattering table to the host: h_theta[ne * ns] (row i = log10 eps node),
+ * h_betamax[ne]. */
+int spx_get_table(const spx_plan* plan, double* h_theta, double* h_betamax);
+
+/* Derived FP64 constants of one segment (host copy), 16 doubles:
+ * Lambda, E_max, s_max, a_mm, eps_per_eV, n_mm3, kT, E_th, lam_th, PhiA, QB, dPhi,
+ * mu_red, vth, vg, z_mid. */
+int spx_segment_info(const spx_plan* plan, int32_t seg, double* h_out16);
+
+/* Philox4x32-10 blocks on the device: d_out[4i..4i+3] = philox(d_ctr[4i..4i+3], key). */
+int spx_philox(const uint32_t* d_ctr, uint32_t key_lo, uint32_t key_hi, uint32_t* d_out, uint64_t n,
+               void* stream);
+
+/* Measurement-area centres (host): lattice points (pitch*i, pitch*j) closest to the
+ * substrate centre, ties in distance ordered by polar angle in [0, 2 pi); h_out[2*n_areas]. */
+int spx_area_centres(int32_t n_areas, double pitch, double* h_out);
+
+/* Area average of n_prof profiles on one grid: d_out[p * n_areas + a] = mean of the
+ * profile over the square of half-width `half_width` around centre a, each bin
+ * weighted by its overlap with the square.  d_profiles double[n_prof * nv * nu],
+ * d_centres double[2 * n_areas] (u, v in the grid frame). */
+int spx_area_gather(const double* d_profiles, int32_t n_prof, int32_t nu, int32_t nv, double half_u,
+                    double half_v, const double* d_centres, int32_t n_areas, double half_width,
+                    double* d_out, void* stream);
+
+/* Composition map, FP32 (Methods, conversion of arrival fractions to at.%):
+ *   w[b,k]   = (a[k] P[b,k] + bb[k]) rho[k] / (M[k] fref[k])
+ *   c[b,j,k] = 100 w[b,k] f[k,j] / sum_l w[b,l] f[l,j]
+ * f [K,J] arrival fraction per area, P [B,K], a/bb/M/rho/fref [K], c [B,J,K]; K <= 64. */
+int spx_comp_forward(const float* d_f, const float* d_a, const float* d_b, const float* d_P,
+                     const float* d_M, const float* d_rho, const float* d_fref, float* d_c,
+                     int32_t B, int32_t J, int32_t K, void* stream);
+
+/* Backward of spx_comp_forward for an upstream gradient d_gc [B,J,K]: gradients of
+ * sum(gc * c) with respect to every input (same shapes).  Each output is written
+ * (not accumulated); deterministic (no floating-point atomics). */
+int spx_comp_backward(const float* d_f, const float* d_a, const float* d_b, const float* d_P,
+                      const float* d_M, const float* d_rho, const float* d_fref, const float* d_gc,
+                      float* d_gf, float* d_ga, float* d_gb, float* d_gP, float* d_gM, float* d_grho,
+                      float* d_gfref, int32_t B, int32_t J, int32_t K, void* stream);
+
+/* Squared Euclidean distance of compositions summed over areas (Results, d_e):
+ * d_loss[b] = sum_{j,k} (c[b,j,k] - ct[b or 0,j,k])^2; ct has B_t = 1 or B rows.
+ * If d_gc is non-NULL it also receives d loss_total / d c scaled by d_gloss[b]
+ * (d_gloss nullable = all ones): gc = 2 (c - ct) gloss[b]. */
+int spx_comp_sqdist(const float* d_c, const float* d_ct, int32_t B_t, const float* d_gloss, float* d_loss,
+                    float* d_gc, int32_t B, int32_t J, int32_t K, void* stream);
+
+void spx_plan_destroy(spx_plan* plan);
+
+/* Description of the last error on this thread; valid until the next spx_* call on it. */
+const char* spx_last_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int32_t spx_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPX_H */

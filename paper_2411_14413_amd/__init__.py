@@ -1,0 +1,312 @@
+"""MI355X-native Monte Carlo transport of sputtered atoms (arXiv 2411.14413).
+
+Python binding of libspx (include/spx.h).  Argument marshalling only: the
+transport, tallies, normalisation, area average and composition map all run in
+hand-written gfx950 HIP kernels.  PyTorch provides device memory and streams.
+
+    import paper_2411_14413_amd as spx
+    plan = spx.Plan(configs)                 # objects with chamber / grid / cathodes
+    out = plan.run(seed=0)                   # dict of torch tensors on the GPU
+    c = spx.CompositionMap.apply(f, a, b, P, M, rho, fref)   # at.%, differentiable
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import _native as N
+from ._native import COUNTER_NAMES, DEPOSITED, ESCAPED, N_COUNTERS, WALL, SpxError, check, lib
+
+__all__ = ["Plan", "philox", "area_centres", "area_gather", "comp_forward", "comp_backward", "comp_sqdist",
+           "CompositionMap", "SquaredDistance", "records_to_numpy", "COUNTER_NAMES", "DEPOSITED", "WALL",
+           "ESCAPED", "SpxError", "version"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def version() -> int:
+    return int(lib().spx_version())
+
+
+def _vec(v):
+    return N.d3(*[float(x) for x in v])
+
+
+def _params(params, precision: int) -> N.Params:
+    p = N.Params()
+    p.theta_min = getattr(params, "theta_min", 0.1) if params is not None else 0.1
+    p.E_th_kT = getattr(params, "E_th_kT", 3.0) if params is not None else 3.0
+    p.event_cap = getattr(params, "event_cap", 1 << 20) if params is not None else 1 << 20
+    p.table_ne = getattr(params, "table_ne", 256) if params is not None else 256
+    p.table_ns = getattr(params, "table_ns", 257) if params is not None else 257
+    p.log_eps_lo = getattr(params, "log_eps_lo", -10.0) if params is not None else -10.0
+    p.log_eps_hi = getattr(params, "log_eps_hi", 0.0) if params is not None else 0.0
+    p.precision = int(precision)
+    return p
+
+
+class Plan:
+    """A validated, device-resident plan for a batch of sputter systems.
+
+    ``configs``: sequence of objects with ``chamber`` (radius, z_lo, z_hi,
+    pressure, T, gas_mass, gas_Z, gas_motion), ``grid`` (center, normal, u_axis,
+    half_u, half_v, shape, nu, nv) and ``cathodes`` (each: center, normal, u_axis,
+    radius, rt_mu, rt_sigma, rt_lo, rt_hi, U_s, E_i, k_cut, mass, Z, cos_coeff,
+    n_particles).  ``precision`` 32 = batched FP32 transport (one persistent
+    launch), 64 = plain FP64 comparator (one launch per segment).
+    """
+
+    def __init__(self, configs: Sequence, params=None, precision: int = 32):
+        L = lib()
+        self.configs = list(configs)
+        self.precision = int(precision)
+        n = len(self.configs)
+        carr = (N.Config * max(n, 1))()
+        self._keep = []
+        for i, cfg in enumerate(self.configs):
+            ch, g = cfg.chamber, cfg.grid
+            C = carr[i]
+            C.chamber = N.Chamber(ch.radius, ch.z_lo, ch.z_hi, ch.pressure, ch.T, ch.gas_mass, int(ch.gas_Z),
+                                  int(ch.gas_motion))
+            C.grid = N.Grid(_vec(g.center), _vec(g.normal), _vec(g.u_axis), g.half_u, g.half_v, int(g.shape),
+                            int(g.nu), int(g.nv), 0)
+            cats = (N.Cathode * len(cfg.cathodes))()
+            for k, c in enumerate(cfg.cathodes):
+                K = cats[k]
+                K.center, K.normal, K.u_axis = _vec(c.center), _vec(c.normal), _vec(c.u_axis)
+                K.radius, K.rt_mu, K.rt_sigma, K.rt_lo, K.rt_hi = c.radius, c.rt_mu, c.rt_sigma, c.rt_lo, c.rt_hi
+                K.U_s, K.E_i, K.k_cut, K.mass, K.Z = c.U_s, c.E_i, c.k_cut, c.mass, int(c.Z)
+                K.cos_coeff = (ctypes.c_double * 6)(*[float(x) for x in c.cos_coeff])
+                K.n_particles = int(c.n_particles)
+            self._keep.append(cats)
+            C.n_cathodes = len(cfg.cathodes)
+            C.cathodes = ctypes.cast(cats, ctypes.POINTER(N.Cathode))
+        self._p = _params(params, precision)
+        h = ctypes.c_void_p()
+        check(L.spx_plan_create(carr, n, ctypes.byref(self._p), ctypes.byref(h)), "spx_plan_create")
+        self._h = h
+        self._keep = None          # the plan holds deep copies
+        nb, nc, npart, ns = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_int32()
+        check(L.spx_plan_query(h, ctypes.byref(nb), ctypes.byref(nc), ctypes.byref(npart), ctypes.byref(ns)),
+              "spx_plan_query")
+        self.n_bins, self.n_counters, self.n_particles, self.n_segments = nb.value, nc.value, npart.value, ns.value
+        bo = (ctypes.c_uint64 * self.n_segments)()
+        fi = (ctypes.c_uint64 * self.n_segments)()
+        check(L.spx_plan_layout(h, bo, fi), "spx_plan_layout")
+        self.bin_off = list(bo)
+        self.first = list(fi)
+        self.shapes = [(cfg.grid.nv, cfg.grid.nu) for cfg in self.configs for _ in cfg.cathodes]
+        self.seg_particles = [int(c.n_particles) for cfg in self.configs for c in cfg.cathodes]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().spx_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    # -- running ---------------------------------------------------------------------------
+    def allocate(self, profiles: bool = True, records: bool = False, device=None) -> Dict[str, object]:
+        torch = _torch()
+        dev = device or torch.device("cuda", torch.cuda.current_device())
+        out = dict(
+            counts=torch.empty(self.n_bins, dtype=torch.int64, device=dev),
+            counters=torch.empty(self.n_counters, dtype=torch.int64, device=dev),
+            profiles=torch.empty(self.n_bins, dtype=torch.float64, device=dev) if profiles else None,
+            records=torch.empty(self.n_particles * N.RECORD_BYTES, dtype=torch.uint8, device=dev) if records else None,
+        )
+        return out
+
+    def run_into(self, seed: int, bufs: Dict[str, object], stream=None) -> None:
+        """Enqueue one run writing into pre-allocated buffers (see allocate)."""
+        check(lib().spx_run(self._h, int(seed) & (2**64 - 1), _ptr(bufs["counts"]), _ptr(bufs["counters"]),
+                            _ptr(bufs.get("profiles")), _ptr(bufs.get("records")), _stream(stream)), "spx_run")
+
+    def run(self, seed: int = 0, profiles: bool = True, records: bool = False, stream=None) -> Dict[str, object]:
+        bufs = self.allocate(profiles=profiles, records=records)
+        self.run_into(seed, bufs, stream)
+        out = dict(bufs)
+        out["counters"] = bufs["counters"].view(self.n_segments, N_COUNTERS)
+        out["counts_seg"] = [bufs["counts"][o:o + nv * nu].view(nv, nu) for o, (nv, nu) in
+                             zip(self.bin_off, self.shapes)]
+        if profiles:
+            out["profiles_seg"] = [bufs["profiles"][o:o + nv * nu].view(nv, nu) for o, (nv, nu) in
+                                   zip(self.bin_off, self.shapes)]
+        return out
+
+    # -- tuning ----------------------------------------------------------------------------
+    def autotune(self, stream=None):
+        check(lib().spx_autotune(self._h, _stream(stream)), "spx_autotune")
+        return self.launch
+
+    @property
+    def launch(self):
+        b, t, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().spx_get_launch(self._h, ctypes.byref(b), ctypes.byref(t), ctypes.byref(r)), "spx_get_launch")
+        return dict(blocks=b.value, threads=t.value, refill_min=r.value)
+
+    def set_launch(self, blocks: int = 0, threads: int = 256, refill_min: int = 1):
+        check(lib().spx_set_launch(self._h, int(blocks), int(threads), int(refill_min)), "spx_set_launch")
+        return self.launch
+
+    # -- introspection ---------------------------------------------------------------------
+    def table(self):
+        ne, ns = self._p.table_ne, self._p.table_ns
+        th = np.empty(ne * ns)
+        bm = np.empty(ne)
+        dp = ctypes.POINTER(ctypes.c_double)
+        check(lib().spx_get_table(self._h, th.ctypes.data_as(dp), bm.ctypes.data_as(dp)), "spx_get_table")
+        return th.reshape(ne, ns), bm
+
+    def segment_info(self, seg: int = 0) -> Dict[str, float]:
+        out = (ctypes.c_double * 16)()
+        check(lib().spx_segment_info(self._h, int(seg), out), "spx_segment_info")
+        names = ("Lambda", "E_max", "s_max", "a_mm", "eps_per_eV", "n_mm3", "kT", "E_th", "lam_th", "PhiA", "QB",
+                 "dPhi", "mu_red", "vth", "vg", "z_mid")
+        return dict(zip(names, list(out)))
+
+
+RECORD_DTYPE = np.dtype([("x", "<f8"), ("y", "<f8"), ("z", "<f8"), ("E", "<f8"), ("state", "<u4"),
+                         ("bin", "<u4"), ("events", "<u4"), ("diffusive", "<u4")])
+
+
+def records_to_numpy(rec_bytes) -> np.ndarray:
+    """Host structured array (x, y, z, E, state, bin, events, diffusive) from a record buffer."""
+    a = rec_bytes.detach().cpu().numpy() if hasattr(rec_bytes, "detach") else np.asarray(rec_bytes)
+    return a.view(RECORD_DTYPE)
+
+
+def philox(ctr, seed: int, stream=None):
+    """Philox4x32-10 blocks of an [n, 4] int32/uint32 CUDA tensor of counters."""
+    torch = _torch()
+    c = ctr.contiguous()
+    out = torch.empty_like(c)
+    check(lib().spx_philox(_ptr(c), int(seed) & 0xFFFFFFFF, (int(seed) >> 32) & 0xFFFFFFFF, _ptr(out), c.shape[0],
+                           _stream(stream)), "spx_philox")
+    return out
+
+
+def area_centres(n_areas: int = 342, pitch: float = 4.5) -> np.ndarray:
+    out = np.empty(2 * n_areas)
+    check(lib().spx_area_centres(int(n_areas), float(pitch), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+          "spx_area_centres")
+    return out.reshape(n_areas, 2)
+
+
+def area_gather(profiles, grid, centres, half_width: float = 2.25, stream=None):
+    """Area averages [n_prof, n_areas] of float64 CUDA profiles [n_prof, nv, nu] (or [nv, nu])."""
+    torch = _torch()
+    p = profiles.contiguous()
+    if p.dim() == 2:
+        p = p.unsqueeze(0)
+    cen = torch.as_tensor(np.asarray(centres, dtype=np.float64), device=p.device).contiguous()
+    out = torch.empty(p.shape[0], cen.shape[0], dtype=torch.float64, device=p.device)
+    check(lib().spx_area_gather(_ptr(p), p.shape[0], int(grid.nu), int(grid.nv), float(grid.half_u),
+                                float(grid.half_v), _ptr(cen), cen.shape[0], float(half_width), _ptr(out),
+                                _stream(stream)), "spx_area_gather")
+    return out
+
+
+def _f32(t):
+    return t.detach().contiguous().float() if t.dtype != _torch().float32 else t.detach().contiguous()
+
+
+def comp_forward(f, a, b, P, M, rho, fref, stream=None):
+    torch = _torch()
+    f, a, b, P, M, rho, fref = (_f32(x) for x in (f, a, b, P, M, rho, fref))
+    K, J = f.shape
+    B = P.shape[0]
+    c = torch.empty(B, J, K, dtype=torch.float32, device=f.device)
+    check(lib().spx_comp_forward(_ptr(f), _ptr(a), _ptr(b), _ptr(P), _ptr(M), _ptr(rho), _ptr(fref), _ptr(c), B, J,
+                                 K, _stream(stream)), "spx_comp_forward")
+    return c
+
+
+def comp_backward(f, a, b, P, M, rho, fref, gc, stream=None):
+    torch = _torch()
+    f, a, b, P, M, rho, fref, gc = (_f32(x) for x in (f, a, b, P, M, rho, fref, gc))
+    K, J = f.shape
+    B = P.shape[0]
+    g = {k: torch.empty_like(v) for k, v in dict(f=f, a=a, b=b, P=P, M=M, rho=rho, fref=fref).items()}
+    check(lib().spx_comp_backward(_ptr(f), _ptr(a), _ptr(b), _ptr(P), _ptr(M), _ptr(rho), _ptr(fref), _ptr(gc),
+                                  _ptr(g["f"]), _ptr(g["a"]), _ptr(g["b"]), _ptr(g["P"]), _ptr(g["M"]),
+                                  _ptr(g["rho"]), _ptr(g["fref"]), B, J, K, _stream(stream)), "spx_comp_backward")
+    return g
+
+
+def comp_sqdist(c, ct, gloss=None, want_grad: bool = False, stream=None):
+    """Per-row squared Euclidean distance sum_{j,k} (c - ct)^2 and optionally 2 (c - ct) gloss."""
+    torch = _torch()
+    c, ct = _f32(c), _f32(ct)
+    if ct.dim() == 2:
+        ct = ct.unsqueeze(0)
+    B, J, K = c.shape
+    loss = torch.empty(B, dtype=torch.float32, device=c.device)
+    gc = torch.empty_like(c) if want_grad else None
+    gl = _f32(gloss) if gloss is not None else None
+    check(lib().spx_comp_sqdist(_ptr(c), _ptr(ct), ct.shape[0], _ptr(gl), _ptr(loss), _ptr(gc), B, J, K,
+                                _stream(stream)), "spx_comp_sqdist")
+    return (loss, gc) if want_grad else loss
+
+
+def _autograd_classes():
+    torch = _torch()
+
+    class CompositionMap(torch.autograd.Function):
+        """at.% [B, J, K] from arrival fractions f [K, J], rates a P + b, masses M,
+        densities rho and calibration values fref; backward by spx_comp_backward."""
+
+        @staticmethod
+        def forward(ctx, f, a, b, P, M, rho, fref):
+            ctx.save_for_backward(f, a, b, P, M, rho, fref)
+            return comp_forward(f, a, b, P, M, rho, fref)
+
+        @staticmethod
+        def backward(ctx, gc):
+            f, a, b, P, M, rho, fref = ctx.saved_tensors
+            g = comp_backward(f, a, b, P, M, rho, fref, gc)
+            outs = []
+            for name, t in zip(("f", "a", "b", "P", "M", "rho", "fref"), (f, a, b, P, M, rho, fref)):
+                outs.append(g[name].to(t.dtype) if ctx.needs_input_grad[len(outs)] else None)
+            return tuple(outs)
+
+    class SquaredDistance(torch.autograd.Function):
+        """Per-row d_e^2 summed over areas: sum_{j,k} (c - c*)^2; c* is a constant target."""
+
+        @staticmethod
+        def forward(ctx, c, ct):
+            ctx.save_for_backward(c, ct)
+            return comp_sqdist(c, ct)
+
+        @staticmethod
+        def backward(ctx, gloss):
+            c, ct = ctx.saved_tensors
+            _, gc = comp_sqdist(c, ct, gloss=gloss, want_grad=True)
+            return gc.to(c.dtype), None
+
+    return CompositionMap, SquaredDistance
+
+
+def __getattr__(name):
+    if name in ("CompositionMap", "SquaredDistance"):
+        cm, sd = _autograd_classes()
+        globals()["CompositionMap"], globals()["SquaredDistance"] = cm, sd
+        return globals()[name]
+    raise AttributeError(name)

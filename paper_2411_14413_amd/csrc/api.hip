@@ -1,0 +1,664 @@
+// api.hip -- host runtime of libspx: validation, per-segment constants, plan
+// memory, the FP32 graph replay, the autotuner and the C-ABI entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "spx_host.hpp"
+
+namespace spx {
+
+namespace {
+thread_local std::string g_error;
+
+constexpr double KB_EV = 8.617333262e-5;     // eV/K
+constexpr double KB_J = 1.380649e-23;        // J/K
+constexpr double E2 = 14.3996454784;         // e^2/(4 pi eps0), eV Angstrom
+constexpr double A0 = 0.529177210903;        // Bohr radius, Angstrom
+constexpr double PI = 3.14159265358979323846;
+
+double norm_cdf(double z) { return 0.5 * std::erfc(-z / std::sqrt(2.0)); }
+void cross(const double* a, const double* b, double* c)
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+double dot(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+bool unit(const double* a) { return std::fabs(std::sqrt(dot(a, a)) - 1.0) < 1e-9; }
+bool inside_chamber(const spx_chamber& ch, const double* p)
+{
+    return std::hypot(p[0], p[1]) <= ch.radius * (1.0 + 1e-12) && p[2] >= ch.z_lo && p[2] <= ch.z_hi;
+}
+// Every boundary point of a disc (centre c, axes u, v, radius R) inside the chamber.
+bool disc_inside(const spx_chamber& ch, const double* c, const double* u, const double* v, double R)
+{
+    for (int k = 0; k < 720; ++k) {
+        const double a = 2.0 * PI * k / 720.0;
+        double p[3];
+        for (int i = 0; i < 3; ++i) p[i] = c[i] + R * (std::cos(a) * u[i] + std::sin(a) * v[i]);
+        if (!inside_chamber(ch, p)) return false;
+    }
+    return inside_chamber(ch, c);
+}
+}  // namespace
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+static int fail(const std::string& msg)
+{
+    set_error(msg);
+    return SPX_EINVAL;
+}
+
+static int validate(const spx_config* cfgs, int n_cfgs, const spx_params* p)
+{
+    if (!cfgs || !p) return fail("null configuration or parameter pointer");
+    if (n_cfgs < 1 || n_cfgs >= (1 << 24)) return fail("n_cfgs must be in [1, 2^24)");
+    if (!(p->theta_min > 0.0 && p->theta_min < PI)) return fail("theta_min must be in (0, pi)");
+    if (!(p->E_th_kT > 0.0)) return fail("E_th_kT must be > 0");
+    if (p->event_cap < 1) return fail("event_cap must be >= 1");
+    if (p->table_ne < 2 || p->table_ns < 2 || (int64_t)p->table_ne * p->table_ns > (1 << 22))
+        return fail("table sizes must be >= 2 and ne*ns <= 2^22");
+    if (!(p->log_eps_lo < p->log_eps_hi)) return fail("log_eps_lo must be < log_eps_hi");
+    if (p->precision != 32 && p->precision != 64) return fail("precision must be 32 or 64");
+    uint64_t total = 0;
+    for (int c = 0; c < n_cfgs; ++c) {
+        const spx_config& C = cfgs[c];
+        const std::string w = "config " + std::to_string(c) + ": ";
+        const spx_chamber& ch = C.chamber;
+        if (!(ch.radius > 0.0) || !(ch.z_hi > ch.z_lo)) return fail(w + "chamber needs radius > 0 and z_hi > z_lo");
+        if (!(ch.pressure >= 0.0)) return fail(w + "pressure must be >= 0");
+        if (!(ch.T > 0.0)) return fail(w + "temperature must be > 0");
+        if (!(ch.gas_mass > 0.0) || ch.gas_Z < 1) return fail(w + "gas mass and Z must be positive");
+        const spx_grid& g = C.grid;
+        if (!unit(g.normal) || !unit(g.u_axis) || std::fabs(dot(g.normal, g.u_axis)) > 1e-9)
+            return fail(w + "substrate normal and u_axis must be orthonormal");
+        if (!(g.half_u > 0.0) || !(g.half_v > 0.0)) return fail(w + "substrate half sizes must be > 0");
+        if (g.shape != 0 && g.shape != 1) return fail(w + "substrate shape must be 0 or 1");
+        if (g.shape == 1 && g.half_v != g.half_u) return fail(w + "disc substrate needs half_v == half_u");
+        if (g.nu < 1 || g.nv < 1 || (int64_t)g.nu * g.nv > (1 << 24)) return fail(w + "need 1 <= nu*nv <= 2^24");
+        {
+            double gv[3];
+            cross(g.normal, g.u_axis, gv);
+            if (g.shape == 0) {
+                for (int sx = -1; sx <= 1; sx += 2)
+                    for (int sy = -1; sy <= 1; sy += 2) {
+                        double q[3];
+                        for (int i = 0; i < 3; ++i) q[i] = g.center[i] + sx * g.half_u * g.u_axis[i] + sy * g.half_v * gv[i];
+                        if (!inside_chamber(ch, q)) return fail(w + "substrate outside the chamber");
+                    }
+            } else if (!disc_inside(ch, g.center, g.u_axis, gv, g.half_u)) {
+                return fail(w + "substrate outside the chamber");
+            }
+        }
+        if (C.n_cathodes < 1 || C.n_cathodes > 255 || !C.cathodes) return fail(w + "need 1..255 cathodes");
+        for (int k = 0; k < C.n_cathodes; ++k) {
+            const spx_cathode& K = C.cathodes[k];
+            const std::string wk = w + "cathode " + std::to_string(k) + ": ";
+            if (!unit(K.normal) || !unit(K.u_axis) || std::fabs(dot(K.normal, K.u_axis)) > 1e-9)
+                return fail(wk + "normal and u_axis must be orthonormal");
+            if (!(K.radius > 0.0)) return fail(wk + "radius must be > 0");
+            double kv[3];
+            cross(K.normal, K.u_axis, kv);
+            if (!disc_inside(ch, K.center, K.u_axis, kv, K.radius)) return fail(wk + "target disc outside the chamber");
+            if (!(K.rt_sigma > 0.0) || !(K.rt_lo < K.rt_hi) || K.rt_lo < 0.0 || K.rt_hi > K.radius)
+                return fail(wk + "racetrack needs sigma > 0 and 0 <= rt_lo < rt_hi <= radius");
+            if (!(K.U_s > 0.0) || !(K.E_i > 0.0) || !(K.k_cut > 0.0)) return fail(wk + "U_s, E_i, k_cut must be > 0");
+            if (!(K.mass > 0.0) || K.Z < 1) return fail(wk + "mass and Z must be positive");
+            const double lam = 4.0 * K.mass * ch.gas_mass / ((K.mass + ch.gas_mass) * (K.mass + ch.gas_mass));
+            if (!(K.k_cut * lam * K.E_i - K.U_s > 0.0)) return fail(wk + "E_max = k Lambda E_i - U_s must be > 0");
+            const double cosine[6] = {0, 1, 0, 0, 0, 0};
+            for (int i = 0; i < 6; ++i)
+                if (K.cos_coeff[i] != cosine[i]) return fail(wk + "only the cosine emission law {0,1,0,0,0,0} is supported");
+            if (K.n_particles >= (1ull << 32)) return fail(wk + "n_particles must be < 2^32");
+            total += K.n_particles;
+        }
+    }
+    if (total == 0) return fail("every cathode has n_particles == 0");
+    return SPX_OK;
+}
+
+// Derive the FP64 constants of every segment (the table must exist for lam_th).
+static void derive(Plan* P, const spx_config* cfgs, int n_cfgs)
+{
+    const spx_params& pr = P->params;
+    for (int c = 0; c < n_cfgs; ++c) {
+        const spx_config& C = cfgs[c];
+        const spx_chamber& ch = C.chamber;
+        const spx_grid& g = C.grid;
+        for (int k = 0; k < C.n_cathodes; ++k) {
+            const spx_cathode& K = C.cathodes[k];
+            SegHost s{};
+            s.cfg = c;
+            s.cath = k;
+            s.z_mid = 0.5 * (ch.z_lo + ch.z_hi);
+            for (int i = 0; i < 3; ++i) {
+                s.cat_c[i] = K.center[i] - (i == 2 ? s.z_mid : 0.0);
+                s.cat_n[i] = K.normal[i];
+                s.cat_u[i] = K.u_axis[i];
+                s.sub_c[i] = g.center[i] - (i == 2 ? s.z_mid : 0.0);
+                s.sub_n[i] = g.normal[i];
+                s.sub_u[i] = g.u_axis[i];
+            }
+            cross(s.cat_n, s.cat_u, s.cat_v);
+            cross(s.sub_n, s.sub_u, s.sub_v);
+            s.cat_R = K.radius;
+            s.half_u = g.half_u;
+            s.half_v = g.half_v;
+            s.shape = g.shape;
+            s.nu = g.nu;
+            s.nv = g.nv;
+            s.du = 2.0 * g.half_u / g.nu;
+            s.dv = 2.0 * g.half_v / g.nv;
+            s.ch_R = ch.radius;
+            s.zlo = ch.z_lo - s.z_mid;
+            s.zhi = ch.z_hi - s.z_mid;
+            s.rt_mu = K.rt_mu;
+            s.rt_sig = K.rt_sigma;
+            const double al = (K.rt_lo - K.rt_mu) / K.rt_sigma, be = (K.rt_hi - K.rt_mu) / K.rt_sigma;
+            s.PhiA = norm_cdf(al);
+            s.QB = norm_cdf(-be);
+            s.dPhi = norm_cdf(be) - s.PhiA;
+            s.Ms = K.mass;
+            s.Mg = ch.gas_mass;
+            s.Us = K.U_s;
+            s.Lambda = 4.0 * s.Ms * s.Mg / ((s.Ms + s.Mg) * (s.Ms + s.Mg));
+            s.Emax = K.k_cut * s.Lambda * K.E_i - s.Us;
+            s.smax = s.Emax / (s.Emax + s.Us);
+            const double a_ang = 0.8853 * A0 * std::pow(std::sqrt((double)K.Z) + std::sqrt((double)ch.gas_Z), -2.0 / 3.0);
+            s.a_mm = a_ang * 1e-7;
+            s.eps_per_eV = a_ang / ((double)K.Z * (double)ch.gas_Z * E2);
+            s.mu_red = s.Ms * s.Mg / (s.Ms + s.Mg);
+            s.pressure = ch.pressure;
+            s.n_mm3 = ch.pressure / (KB_J * ch.T) * 1e-9;
+            s.kT = KB_EV * ch.T;
+            s.vth = std::sqrt(s.kT / s.Mg);
+            s.vg = std::sqrt(2.0 * s.kT / s.Mg);
+            s.E_th = pr.E_th_kT * s.kT;
+            s.gas_motion = ch.gas_motion ? 1 : 0;
+            s.N = K.n_particles;
+            P->seg.push_back(s);
+        }
+    }
+}
+
+// beta_max(eps) linear in log10(eps) on the FP64 table (host copy).
+static double betamax_host(const Plan* P, double eps)
+{
+    const spx_params& pr = P->params;
+    const int ne = pr.table_ne;
+    double x = (std::log10(eps) - pr.log_eps_lo) / (pr.log_eps_hi - pr.log_eps_lo) * (ne - 1);
+    x = x > 0.0 ? x : 0.0;
+    x = x < ne - 1 ? x : ne - 1;
+    int i = (int)std::floor(x);
+    i = i < ne - 2 ? i : ne - 2;
+    const double f = x - i;
+    return P->h_betamax[i] * (1.0 - f) + P->h_betamax[i + 1] * f;
+}
+
+template <typename R> static SegDev<R> to_device(const Plan* P, const SegHost& s)
+{
+    const spx_params& pr = P->params;
+    SegDev<R> d{};
+    for (int i = 0; i < 3; ++i) {
+        d.cat_c[i] = (R)s.cat_c[i];
+        d.cat_n[i] = (R)s.cat_n[i];
+        d.cat_u[i] = (R)s.cat_u[i];
+        d.cat_v[i] = (R)s.cat_v[i];
+        d.sub_c[i] = (R)s.sub_c[i];
+        d.sub_n[i] = (R)s.sub_n[i];
+        d.sub_u[i] = (R)s.sub_u[i];
+        d.sub_v[i] = (R)s.sub_v[i];
+    }
+    d.cat_R2 = (R)(s.cat_R * s.cat_R);
+    d.half_u = (R)s.half_u;
+    d.half_v = (R)s.half_v;
+    d.inv_du = (R)(1.0 / s.du);
+    d.inv_dv = (R)(1.0 / s.dv);
+    d.sub_R2 = (R)(s.half_u * s.half_u);
+    d.ch_R2 = (R)(s.ch_R * s.ch_R);
+    d.zlo = (R)s.zlo;
+    d.zhi = (R)s.zhi;
+    d.rt_mu = (R)s.rt_mu;
+    d.rt_sig = (R)s.rt_sig;
+    d.PhiA = (R)s.PhiA;
+    d.QB = (R)s.QB;
+    d.dPhi = (R)s.dPhi;
+    d.Us = (R)s.Us;
+    d.smax = (R)s.smax;
+    d.two_over_Ms = (R)(2.0 / s.Ms);
+    d.half_Ms = (R)(0.5 * s.Ms);
+    d.Ms_frac = (R)(s.Ms / (s.Ms + s.Mg));
+    d.Mg_frac = (R)(s.Mg / (s.Ms + s.Mg));
+    d.half_mu_red = (R)(0.5 * s.mu_red);
+    const double sc = (pr.table_ne - 1) / (pr.log_eps_hi - pr.log_eps_lo);
+    d.xo_coll = (R)((std::log10(s.eps_per_eV) - pr.log_eps_lo) * sc);
+    d.xo_stat = (R)((std::log10(s.eps_per_eV * s.Mg / (s.Ms + s.Mg)) - pr.log_eps_lo) * sc);
+    d.n_pia2 = (R)(s.n_mm3 * PI * s.a_mm * s.a_mm);
+    d.vth = (R)s.vth;
+    d.inv_vg = (R)(1.0 / s.vg);
+    d.vg = (R)s.vg;
+    d.E_th = (R)s.E_th;
+    d.lam_th = (R)s.lam_th;
+    d.z_mid = (R)s.z_mid;
+    d.shape = s.shape;
+    d.nu = s.nu;
+    d.nv = s.nv;
+    d.gas_motion = s.gas_motion;
+    d.vacuum = s.n_mm3 > 0.0 ? 0 : 1;
+    d.cfgcat = ((uint32_t)s.cfg << 8) | (uint32_t)s.cath;
+    d.bin_off = s.bin_off;
+    d.first_rec = s.first_rec;
+    d.N = s.N;
+    return d;
+}
+
+template <typename T> static int dalloc(T** p, size_t n)
+{
+    if (n == 0) n = 1;
+    hipError_t e = hipMalloc((void**)p, sizeof(T) * n);
+    if (e != hipSuccess) {
+        set_error(std::string("hipMalloc failed: ") + hipGetErrorString(e));
+        return SPX_ENOMEM;
+    }
+    return SPX_OK;
+}
+
+static void release(Plan* P)
+{
+    if (!P) return;
+    if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
+    if (P->graph) (void)hipGraphDestroy(P->graph);
+    void* ptrs[] = {P->d_theta64, P->d_betamax64, P->d_theta32, P->d_betamax32, P->d_seg32, P->d_seg64,
+                    P->d_tfirst,  P->d_torder,    P->d_ticket,  P->d_bin_off,   P->d_seg_norm};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    if (P->work_stream) (void)hipStreamDestroy(P->work_stream);
+    delete P;
+}
+
+static int create(const spx_config* cfgs, int n_cfgs, const spx_params* prm, Plan** out)
+{
+    SPX_TRY(validate(cfgs, n_cfgs, prm));
+    int ndev = 0;
+    SPX_HIP(hipGetDeviceCount(&ndev));
+    if (ndev < 1) {
+        set_error("no HIP device");
+        return SPX_EDEVICE;
+    }
+    int dev = 0;
+    SPX_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    SPX_HIP(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        set_error(std::string("libspx is built for gfx950; current device is ") + prop.gcnArchName);
+        return SPX_EDEVICE;
+    }
+    Plan* P = new Plan();
+    P->device = dev;
+    P->params = *prm;
+    P->n_cu = prop.multiProcessorCount;
+    derive(P, cfgs, n_cfgs);
+    P->n_seg = (int)P->seg.size();
+    uint64_t boff = 0, first = 0;
+    for (auto& s : P->seg) {
+        s.bin_off = boff;
+        s.first_rec = first;
+        P->h_bin_off.push_back(boff);
+        P->h_first.push_back(first);
+        boff += (uint64_t)s.nu * s.nv;
+        first += s.N;
+    }
+    P->n_bins_total = boff;
+    P->n_particles_total = first;
+
+    int rc = SPX_OK;
+    auto chk = [&](int r) {
+        if (rc == SPX_OK && r != SPX_OK) rc = r;
+        return rc == SPX_OK;
+    };
+    const int ne = prm->table_ne, ns = prm->table_ns, n = P->n_seg;
+    if (hipStreamCreateWithFlags(&P->work_stream, hipStreamNonBlocking) != hipSuccess) {
+        set_error("hipStreamCreate failed");
+        release(P);
+        return SPX_EDEVICE;
+    }
+    chk(dalloc(&P->d_theta64, (size_t)ne * ns)) && chk(dalloc(&P->d_betamax64, ne)) &&
+        chk(dalloc(&P->d_theta32, (size_t)ne * ns)) && chk(dalloc(&P->d_betamax32, ne)) &&
+        chk(dalloc(&P->d_seg32, n)) && chk(dalloc(&P->d_seg64, n)) && chk(dalloc(&P->d_tfirst, n + 1)) &&
+        chk(dalloc(&P->d_torder, n)) && chk(dalloc(&P->d_ticket, 1)) && chk(dalloc(&P->d_bin_off, n + 1)) &&
+        chk(dalloc(&P->d_seg_norm, n));
+    if (rc == SPX_OK) rc = build_tables(P);
+    if (rc != SPX_OK) {
+        release(P);
+        return rc;
+    }
+    // thermal mean free path and normalisation from the FP64 table
+    for (auto& s : P->seg) {
+        if (s.n_mm3 > 0.0) {
+            const double bm = betamax_host(P, s.eps_per_eV * 1.5 * s.kT);
+            const double sig = PI * (s.a_mm * bm) * (s.a_mm * bm);
+            s.lam_th = 1.0 / (s.n_mm3 * sig * std::sqrt(1.0 + s.Ms / s.Mg));
+        } else {
+            s.lam_th = INFINITY;
+        }
+        P->seg_norm.push_back(s.N ? 1.0 / ((double)s.N * s.du * s.dv) : 0.0);
+    }
+    std::vector<SegDev<float>> s32;
+    std::vector<SegDev<double>> s64;
+    for (const auto& s : P->seg) {
+        s32.push_back(to_device<float>(P, s));
+        s64.push_back(to_device<double>(P, s));
+    }
+    // ticket order: highest pressure (longest histories) first
+    std::vector<uint32_t> order(n);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t b) { return P->seg[a].pressure > P->seg[b].pressure; });
+    std::vector<uint64_t> tfirst(n + 1, 0);
+    for (int o = 0; o < n; ++o) tfirst[o + 1] = tfirst[o] + P->seg[order[o]].N;
+    P->n_tickets = tfirst[n];
+    std::vector<uint64_t> bo(P->h_bin_off);
+    bo.push_back(P->n_bins_total);
+    hipStream_t st = P->work_stream;
+    bool ok = hipMemcpyAsync(P->d_seg32, s32.data(), sizeof(SegDev<float>) * n, hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(P->d_seg64, s64.data(), sizeof(SegDev<double>) * n, hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(P->d_tfirst, tfirst.data(), sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(P->d_torder, order.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(P->d_bin_off, bo.data(), sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipMemcpyAsync(P->d_seg_norm, P->seg_norm.data(), sizeof(double) * n, hipMemcpyHostToDevice, st) == hipSuccess &&
+              hipStreamSynchronize(st) == hipSuccess;
+    if (!ok) {
+        set_error("copying plan constants to the device failed");
+        release(P);
+        return SPX_EDEVICE;
+    }
+    int bpc = 0;
+    if (occupancy_transport32(P->threads, &bpc) != SPX_OK || bpc < 1) {
+        release(P);
+        set_error("occupancy query failed for the transport kernel");
+        return SPX_EDEVICE;
+    }
+    P->max_blocks_per_cu = bpc;
+    P->blocks = bpc * P->n_cu;
+    *out = P;
+    return SPX_OK;
+}
+
+static int run(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
+               spx_record* d_records, hipStream_t st)
+{
+    if (P->params.precision == 64)
+        return launch_transport64(P, seed, d_counts, d_counters, d_profiles, d_records, st);
+    GraphKey key;
+    key.seed = seed;
+    key.counts = d_counts;
+    key.counters = d_counters;
+    key.profiles = d_profiles;
+    key.records = d_records;
+    key.blocks = P->blocks;
+    key.threads = P->threads;
+    key.refill = P->refill_min;
+    if (!P->graph_exec || !(key == P->graph_key)) {
+        if (P->graph_exec) {
+            SPX_HIP(hipGraphExecDestroy(P->graph_exec));
+            P->graph_exec = nullptr;
+        }
+        if (P->graph) {
+            SPX_HIP(hipGraphDestroy(P->graph));
+            P->graph = nullptr;
+        }
+        SPX_HIP(hipStreamBeginCapture(P->work_stream, hipStreamCaptureModeThreadLocal));
+        const int rc = launch_transport32(P, seed, d_counts, d_counters, d_profiles, d_records, P->work_stream,
+                                          P->d_tfirst, P->n_tickets, P->blocks, P->threads, P->refill_min);
+        hipGraph_t g = nullptr;
+        const hipError_t ec = hipStreamEndCapture(P->work_stream, &g);
+        if (rc != SPX_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        SPX_HIP(ec);
+        P->graph = g;
+        SPX_HIP(hipGraphInstantiate(&P->graph_exec, P->graph, nullptr, nullptr, 0));
+        P->graph_key = key;
+    }
+    SPX_HIP(hipGraphLaunch(P->graph_exec, st));
+    return SPX_OK;
+}
+
+// Time FP32 transport launch shapes on a reduced ticket space (the first n_tune
+// particles of every segment) and keep the fastest.  Outputs go to scratch.
+static int autotune(Plan* P, hipStream_t st)
+{
+    const int n = P->n_seg;
+    const uint64_t per_seg_target = std::max<uint64_t>(4096, (uint64_t)(3.0e6 / n));
+    std::vector<uint64_t> tf(n + 1, 0);
+    std::vector<uint32_t> order(n);
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t b) { return P->seg[a].pressure > P->seg[b].pressure; });
+    for (int o = 0; o < n; ++o) tf[o + 1] = tf[o] + std::min<uint64_t>(P->seg[order[o]].N, per_seg_target);
+    uint64_t *d_tf = nullptr, *d_counts = nullptr, *d_ctr = nullptr;
+    SPX_TRY(dalloc(&d_tf, n + 1));
+    int rc = dalloc(&d_counts, P->n_bins_total);
+    if (rc == SPX_OK) rc = dalloc(&d_ctr, (size_t)n * N_COUNTERS);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == SPX_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = SPX_EDEVICE;
+    if (rc == SPX_OK && hipMemcpyAsync(d_tf, tf.data(), sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = SPX_EDEVICE;
+    float best = 1e30f;
+    int bb = P->blocks, bt = P->threads, br = P->refill_min;
+    const int thread_opts[] = {256, 512, 1024};
+    const int refill_opts[] = {1, 8, 24};
+    for (int t : thread_opts) {
+        if (rc != SPX_OK) break;
+        int bpc = 0;
+        if (occupancy_transport32(t, &bpc) != SPX_OK || bpc < 1) continue;
+        for (int r : refill_opts) {
+            const int blocks = bpc * P->n_cu;
+            float ms_min = 1e30f;
+            for (int rep = 0; rep < 2 && rc == SPX_OK; ++rep) {
+                if (hipEventRecord(e0, st) != hipSuccess) rc = SPX_EDEVICE;
+                if (rc == SPX_OK) rc = launch_transport32(P, 0x5eed, d_counts, d_ctr, nullptr, nullptr, st, d_tf, tf[n],
+                                                          blocks, t, r);
+                if (rc == SPX_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                    rc = SPX_EDEVICE;
+                float ms = 0.f;
+                if (rc == SPX_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms_min = std::min(ms_min, ms);
+            }
+            if (rc == SPX_OK && ms_min < best) {
+                best = ms_min;
+                bb = blocks;
+                bt = t;
+                br = r;
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(d_tf);
+    if (d_counts) (void)hipFree(d_counts);
+    if (d_ctr) (void)hipFree(d_ctr);
+    if (rc != SPX_OK) {
+        if (rc == SPX_EDEVICE) set_error("autotune: HIP error while timing launch shapes");
+        return rc;
+    }
+    P->blocks = bb;
+    P->threads = bt;
+    P->refill_min = br;
+    return SPX_OK;
+}
+
+}  // namespace spx
+
+using namespace spx;
+
+__global__ void k_philox(const uint32_t* __restrict__ ctr, uint32_t k0, uint32_t k1, uint32_t* __restrict__ out,
+                         uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint4 c = make_uint4(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3]);
+    const uint4 r = philox4x32_10(c, k0, k1);
+    out[4 * i] = r.x;
+    out[4 * i + 1] = r.y;
+    out[4 * i + 2] = r.z;
+    out[4 * i + 3] = r.w;
+}
+
+extern "C" {
+
+int spx_plan_create(const spx_config* h_cfgs, int32_t n_cfgs, const spx_params* h_params, spx_plan** out)
+{
+    if (!out) return fail("null output pointer");
+    try {
+        return create(h_cfgs, n_cfgs, h_params, out);
+    } catch (const std::exception& e) {
+        set_error(std::string("spx_plan_create: ") + e.what());
+        return SPX_ENOMEM;
+    }
+}
+
+int spx_plan_query(const spx_plan* P, uint64_t* n_bins_total, uint64_t* n_counters, uint64_t* n_particles_total,
+                   int32_t* n_segments)
+{
+    if (!P) return fail("null plan");
+    if (n_bins_total) *n_bins_total = P->n_bins_total;
+    if (n_counters) *n_counters = (uint64_t)P->n_seg * N_COUNTERS;
+    if (n_particles_total) *n_particles_total = P->n_particles_total;
+    if (n_segments) *n_segments = P->n_seg;
+    return SPX_OK;
+}
+
+int spx_plan_layout(const spx_plan* P, uint64_t* h_bin_off, uint64_t* h_first)
+{
+    if (!P) return fail("null plan");
+    if (h_bin_off) std::memcpy(h_bin_off, P->h_bin_off.data(), sizeof(uint64_t) * P->n_seg);
+    if (h_first) std::memcpy(h_first, P->h_first.data(), sizeof(uint64_t) * P->n_seg);
+    return SPX_OK;
+}
+
+int spx_run(spx_plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
+            spx_record* d_records, void* stream)
+{
+    if (!P) return fail("null plan");
+    if (!d_counts || !d_counters) return fail("spx_run: d_counts and d_counters are required");
+    try {
+        SPX_HIP(hipSetDevice(P->device));
+        return run(P, seed, d_counts, d_counters, d_profiles, d_records, (hipStream_t)stream);
+    } catch (const std::exception& e) {
+        set_error(std::string("spx_run: ") + e.what());
+        return SPX_ENOMEM;
+    }
+}
+
+int spx_autotune(spx_plan* P, void* stream)
+{
+    if (!P) return fail("null plan");
+    if (P->params.precision != 32) return SPX_OK;
+    SPX_HIP(hipSetDevice(P->device));
+    return autotune(P, (hipStream_t)stream);
+}
+
+int spx_get_launch(const spx_plan* P, int32_t* blocks, int32_t* threads, int32_t* refill_min)
+{
+    if (!P) return fail("null plan");
+    if (blocks) *blocks = P->blocks;
+    if (threads) *threads = P->threads;
+    if (refill_min) *refill_min = P->refill_min;
+    return SPX_OK;
+}
+
+int spx_set_launch(spx_plan* P, int32_t blocks, int32_t threads, int32_t refill_min)
+{
+    if (!P) return fail("null plan");
+    if (threads < 64 || threads > 1024 || (threads & 63)) return fail("threads must be a multiple of 64 in [64, 1024]");
+    if (refill_min < 1 || refill_min > 64) return fail("refill_min must be in [1, 64]");
+    int bpc = 0;
+    SPX_TRY(occupancy_transport32(threads, &bpc));
+    if (bpc < 1) return fail("transport kernel does not fit with this block size");
+    // a persistent grid larger than the resident limit would still be correct, but it is never useful
+    const int limit = bpc * P->n_cu;
+    P->blocks = (blocks <= 0 || blocks > limit) ? limit : blocks;
+    P->threads = threads;
+    P->refill_min = refill_min;
+    return SPX_OK;
+}
+
+int spx_get_table(const spx_plan* P, double* h_theta, double* h_betamax)
+{
+    if (!P || !h_theta || !h_betamax) return fail("null argument");
+    const size_t ne = P->params.table_ne, ns = P->params.table_ns;
+    SPX_HIP(hipMemcpyAsync(h_theta, P->d_theta64, sizeof(double) * ne * ns, hipMemcpyDeviceToHost, P->work_stream));
+    SPX_HIP(hipMemcpyAsync(h_betamax, P->d_betamax64, sizeof(double) * ne, hipMemcpyDeviceToHost, P->work_stream));
+    SPX_HIP(hipStreamSynchronize(P->work_stream));
+    return SPX_OK;
+}
+
+int spx_segment_info(const spx_plan* P, int32_t seg, double* out)
+{
+    if (!P || !out) return fail("null argument");
+    if (seg < 0 || seg >= P->n_seg) return fail("segment index out of range");
+    const SegHost& s = P->seg[seg];
+    const double v[16] = {s.Lambda, s.Emax, s.smax, s.a_mm, s.eps_per_eV, s.n_mm3, s.kT, s.E_th,
+                          s.lam_th, s.PhiA, s.QB,   s.dPhi, s.mu_red,     s.vth,   s.vg, s.z_mid};
+    std::memcpy(out, v, sizeof(v));
+    return SPX_OK;
+}
+
+int spx_philox(const uint32_t* d_ctr, uint32_t key_lo, uint32_t key_hi, uint32_t* d_out, uint64_t n, void* stream)
+{
+    if (!d_ctr || !d_out) return fail("null argument");
+    if (n == 0) return SPX_OK;
+    const uint64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffffull) return fail("too many counters");
+    hipLaunchKernelGGL(k_philox, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, d_ctr, key_lo, key_hi,
+                       d_out, n);
+    SPX_HIP(hipGetLastError());
+    return SPX_OK;
+}
+
+int spx_area_centres(int32_t n_areas, double pitch, double* h_out)
+{
+    if (n_areas < 1 || !(pitch > 0.0) || !h_out) return fail("spx_area_centres: invalid arguments");
+    const int m = (int)std::ceil(std::sqrt((double)n_areas)) + 2;
+    struct Pt {
+        int64_t r2;
+        double ang;
+        int i, j;
+    };
+    std::vector<Pt> pts;
+    for (int i = -m; i <= m; ++i)
+        for (int j = -m; j <= m; ++j) {
+            double a = std::atan2((double)j, (double)i);
+            if (a < 0.0) a += 2.0 * PI;
+            pts.push_back({(int64_t)i * i + (int64_t)j * j, a, i, j});
+        }
+    std::sort(pts.begin(), pts.end(), [](const Pt& a, const Pt& b) {
+        return a.r2 != b.r2 ? a.r2 < b.r2 : a.ang < b.ang;
+    });
+    for (int k = 0; k < n_areas; ++k) {
+        h_out[2 * k] = pitch * pts[k].i;
+        h_out[2 * k + 1] = pitch * pts[k].j;
+    }
+    return SPX_OK;
+}
+
+void spx_plan_destroy(spx_plan* P)
+{
+    if (P) (void)hipSetDevice(P->device);
+    release(P);
+}
+
+const char* spx_last_error(void) { return g_error.c_str(); }
+
+int32_t spx_version(void) { return 100; }
+
+}  // extern "C"

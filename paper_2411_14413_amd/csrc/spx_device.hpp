@@ -1,0 +1,439 @@
+// spx_device.hpp -- device-side data layout and the per-event physics of the
+// sputtered-atom transport, written once for R = float (batched transport) and
+// R = double (plain comparator).
+//
+// Method (Thelen et al., arXiv 2411.14413, Methods, "The SIMTRA model" and the
+// calculation paragraph that closes Methods): launch from the racetrack with a
+// Thompson energy cut off at E_max and a cosine emission law; free path
+// -lambda_m ln RN_1; nearest surface hit; otherwise an elastic collision with a gas
+// atom (thermal partner velocity, Moliere-screened Coulomb deflection from a
+// table, binary-collision kinematics); below the thermalisation threshold the atom
+// takes isotropic exponential diffusive steps until it hits a surface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace spx {
+
+enum : int { ST_DEAD = 0, ST_BALLISTIC = 1, ST_DIFFUSIVE = 2 };
+enum : int { HIT_NONE = 0, HIT_DEPOSITED = 1, HIT_WALL = 2, HIT_ESCAPED = 3 };
+enum : int { C_LAUNCHED = 0, C_DEPOSITED, C_WALL, C_ESCAPED, C_COLLISIONS, C_DIFFUSIVE, N_COUNTERS };
+
+// --------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11); the key words are uniform
+// across the launch, so their schedule lives in scalar registers.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+                       (uint32_t)p0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// RN in ]0,1]: ((x >> 8) + 1) * 2^-24, exact in float and double.
+template <typename R> __device__ __forceinline__ R u01(uint32_t x);
+template <> __device__ __forceinline__ float u01<float>(uint32_t x)
+{
+    return (float)((x >> 8) + 1u) * 0x1p-24f;
+}
+template <> __device__ __forceinline__ double u01<double>(uint32_t x)
+{
+    return (double)((x >> 8) + 1u) * 0x1p-24;
+}
+
+// --------------------------------------------------------------------------
+// Math overloads for R.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float m_log(float x) { return logf(x); }
+__device__ __forceinline__ double m_log(double x) { return log(x); }
+__device__ __forceinline__ float m_log2(float x) { return log2f(x); }
+__device__ __forceinline__ double m_log2(double x) { return log2(x); }
+__device__ __forceinline__ float m_exp(float x) { return expf(x); }
+__device__ __forceinline__ double m_exp(double x) { return exp(x); }
+__device__ __forceinline__ float m_erf(float x) { return erff(x); }
+__device__ __forceinline__ double m_erf(double x) { return erf(x); }
+__device__ __forceinline__ float m_ninv(float p) { return normcdfinvf(p); }
+__device__ __forceinline__ double m_ninv(double p) { return normcdfinv(p); }
+__device__ __forceinline__ float m_floor(float x) { return floorf(x); }
+__device__ __forceinline__ double m_floor(double x) { return floor(x); }
+__device__ __forceinline__ bool m_finite(float x) { return isfinite(x); }
+__device__ __forceinline__ bool m_finite(double x) { return isfinite(x); }
+// sin and cos of 2 pi u for u in ]0, 1]
+__device__ __forceinline__ void m_sincos2pi(float u, float* s, float* c) { sincospif(2.0f * u, s, c); }
+__device__ __forceinline__ void m_sincos2pi(double u, double* s, double* c) { sincospi(2.0 * u, s, c); }
+__device__ __forceinline__ void m_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
+__device__ __forceinline__ void m_sincos(double x, double* s, double* c) { sincos(x, s, c); }
+template <typename R> __device__ __forceinline__ R m_inf();
+template <> __device__ __forceinline__ float m_inf<float>() { return __builtin_huge_valf(); }
+template <> __device__ __forceinline__ double m_inf<double>() { return __builtin_huge_val(); }
+
+// --------------------------------------------------------------------------
+// Per-segment constants, derived on the host in double precision.
+// Positions are in the chamber-centred frame: z' = z - z_mid.
+// --------------------------------------------------------------------------
+template <typename R> struct SegDev {
+    R cat_c[3], cat_n[3], cat_u[3], cat_v[3];
+    R cat_R2;
+    R sub_c[3], sub_n[3], sub_u[3], sub_v[3];
+    R half_u, half_v, inv_du, inv_dv, sub_R2;
+    R ch_R2, zlo, zhi;
+    R rt_mu, rt_sig, PhiA, QB, dPhi;      // racetrack truncated normal
+    R Us, smax;                           // Thompson inverse CDF
+    R two_over_Ms, half_Ms;               // v = sqrt(2E/Ms), E = Ms v^2 / 2
+    R Ms_frac, Mg_frac;                   // Ms/(Ms+Mg), Mg/(Ms+Mg)
+    R half_mu_red;                        // E_r = mu |g|^2 / 2
+    R xo_coll;                            // table index offset for eps = eps_per_eV * E_r
+    R xo_stat;                            // ... for eps of a gas atom at rest: E_r = E Mg/(Ms+Mg)
+    R n_pia2;                             // n pi a^2: n sigma = n_pia2 * beta_max^2
+    R vth, inv_vg, vg;                    // Maxwellian component sd; mean-speed scale
+    R E_th, lam_th;
+    R z_mid;                              // chamber-frame origin along z (world z = z' + z_mid)
+    int32_t shape, nu, nv, gas_motion;
+    int32_t vacuum, pad0;
+    uint32_t cfgcat;                      // (config << 8) | cathode: third Philox counter word
+    uint32_t pad1;
+    uint64_t bin_off;                     // first bin of this segment in the tally
+    uint64_t first_rec;                   // first record of this segment
+    uint64_t N;                           // particles
+};
+
+template <typename R> struct TabDev {
+    const R* theta;    // [ne][ns]
+    const R* betamax;  // [ne]
+    R xs;              // index per log2(eps): (ne-1) / ((hi - lo) log2(10))
+    int32_t ne, ns;
+};
+
+// Linear interpolation of beta_max at table coordinate x (clamped).
+template <typename R> __device__ __forceinline__ R tab_betamax(const TabDev<R>& tb, R x)
+{
+    const R xmax = (R)(tb.ne - 1);
+    x = (x > (R)0) ? x : (R)0;            // also maps NaN to 0
+    x = (x < xmax) ? x : xmax;
+    int i = (int)m_floor(x);
+    i = (i < tb.ne - 2) ? i : tb.ne - 2;
+    const R f = x - (R)i;
+    return tb.betamax[i] * ((R)1 - f) + tb.betamax[i + 1] * f;
+}
+
+// Bilinear theta_cm at table coordinates (x along log10 eps, s = b/b_max).
+template <typename R> __device__ __forceinline__ R tab_theta(const TabDev<R>& tb, R x, R s)
+{
+    const R xmax = (R)(tb.ne - 1), ymax = (R)(tb.ns - 1);
+    x = (x > (R)0) ? x : (R)0;
+    x = (x < xmax) ? x : xmax;
+    int i = (int)m_floor(x);
+    i = (i < tb.ne - 2) ? i : tb.ne - 2;
+    const R fx = x - (R)i;
+    R y = s * ymax;
+    y = (y > (R)0) ? y : (R)0;
+    y = (y < ymax) ? y : ymax;
+    int j = (int)m_floor(y);
+    j = (j < tb.ns - 2) ? j : tb.ns - 2;
+    const R fy = y - (R)j;
+    const R* T = tb.theta + (size_t)i * tb.ns + j;
+    const R t00 = T[0], t01 = T[1], t10 = T[tb.ns], t11 = T[tb.ns + 1];
+    return ((R)1 - fx) * ((R)1 - fy) * t00 + fx * ((R)1 - fy) * t10 + ((R)1 - fx) * fy * t01 + fx * fy * t11;
+}
+
+template <typename R> __device__ __forceinline__ R dot3(const R* a, const R* b)
+{
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// --------------------------------------------------------------------------
+// Launch (event 0): sub-block 0 -> u0..u3, sub-block 1 -> u4.
+// --------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void launch(const SegDev<R>& s, uint4 r0, uint4 r1, R* x, R* d, R& E)
+{
+    const R u0 = u01<R>(r0.x), u1 = u01<R>(r0.y), u2 = u01<R>(r0.z), u3 = u01<R>(r0.w);
+    const R u4 = u01<R>(r1.x);
+    // racetrack radius: inverse CDF of the truncated normal; the upper half takes the
+    // complement so that no precision is lost near 1
+    R z;
+    const R P = s.PhiA + u0 * s.dPhi;
+    if (P <= (R)0.5) {
+        z = m_ninv(P);
+    } else {
+        const R Q = s.QB + ((R)1 - u0) * s.dPhi;
+        z = -m_ninv(Q);
+    }
+    const R rr = s.rt_mu + s.rt_sig * z;
+    R sp, cp;
+    m_sincos2pi(u1, &sp, &cp);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) x[i] = s.cat_c[i] + rr * (cp * s.cat_u[i] + sp * s.cat_v[i]);
+    // Thompson energy: [E/(E+U_s)]^2 proportional to RN up to the cut-off
+    const R se = m_sqrt(u2) * s.smax;
+    E = s.Us * se / ((R)1 - se);
+    // cosine emission: cos(theta) = sqrt(RN)
+    const R mu = m_sqrt(u3), st = m_sqrt((R)1 - u3);
+    R sf, cf;
+    m_sincos2pi(u4, &sf, &cf);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) d[i] = mu * s.cat_n[i] + st * (cf * s.cat_u[i] + sf * s.cat_v[i]);
+}
+
+// Mean free path at energy E.
+template <typename R>
+__device__ __forceinline__ R lambda_m(const SegDev<R>& s, const TabDev<R>& tb, R E)
+{
+    const R bm = tab_betamax(tb, m_log2(E) * tb.xs + s.xo_stat);
+    const R nsig = s.n_pia2 * bm * bm;
+    if (!s.gas_motion) return (R)1 / nsig;
+    // moving gas: the collision rate uses the Maxwellian mean relative speed <g>(v)
+    const R v = m_sqrt(E * s.two_over_Ms);
+    const R xx = v * s.inv_vg;
+    const R g = s.vg * ((xx + (R)0.5 / xx) * m_erf(xx) + m_exp(-xx * xx) * (R)0.56418958354775628695);
+    return v / (nsig * g);
+}
+
+struct Hit {
+    int state;     // HIT_NONE / HIT_DEPOSITED / HIT_WALL
+    int bin;
+};
+
+// Nearest surface with 0 < t <= ell; exact ties keep substrate, then cathode, then chamber.
+template <typename R>
+__device__ __forceinline__ Hit hit_test(const SegDev<R>& s, const R* x, const R* d, R ell, R& t_hit, bool first)
+{
+    R best = m_inf<R>();
+    int state = HIT_NONE, bin = -1;
+    {   // substrate plate
+        const R dn = dot3(d, s.sub_n);
+        if (dn != (R)0) {
+            const R w[3] = {s.sub_c[0] - x[0], s.sub_c[1] - x[1], s.sub_c[2] - x[2]};
+            const R t = dot3(w, s.sub_n) / dn;
+            if (t > (R)0) {
+                const R q[3] = {t * d[0] - w[0], t * d[1] - w[1], t * d[2] - w[2]};
+                const R qu = dot3(q, s.sub_u), qv = dot3(q, s.sub_v);
+                const bool inside = (s.shape == 0) ? (fabs(qu) <= s.half_u && fabs(qv) <= s.half_v)
+                                                   : (qu * qu + qv * qv <= s.sub_R2);
+                if (inside) {
+                    best = t;
+                    if (dn < (R)0) {
+                        int iu = (int)m_floor((qu + s.half_u) * s.inv_du);
+                        int iv = (int)m_floor((qv + s.half_v) * s.inv_dv);
+                        iu = iu < 0 ? 0 : (iu > s.nu - 1 ? s.nu - 1 : iu);
+                        iv = iv < 0 ? 0 : (iv > s.nv - 1 ? s.nv - 1 : iv);
+                        state = HIT_DEPOSITED;
+                        bin = iv * s.nu + iu;
+                    } else {
+                        state = HIT_WALL;
+                    }
+                }
+            }
+        }
+    }
+    // emitting cathode disc (both faces absorb).  The first flight starts on the target
+    // plane and a line meets a plane once, so on that flight the target is not tested.
+    if (!first) {
+        const R dn = dot3(d, s.cat_n);
+        if (dn != (R)0) {
+            const R w[3] = {s.cat_c[0] - x[0], s.cat_c[1] - x[1], s.cat_c[2] - x[2]};
+            const R t = dot3(w, s.cat_n) / dn;
+            if (t > (R)0 && t < best) {
+                const R q[3] = {t * d[0] - w[0], t * d[1] - w[1], t * d[2] - w[2]};
+                const R qu = dot3(q, s.cat_u), qv = dot3(q, s.cat_v);
+                if (qu * qu + qv * qv <= s.cat_R2) {
+                    best = t;
+                    state = HIT_WALL;
+                    bin = -1;
+                }
+            }
+        }
+    }
+    {   // chamber: cylinder side and caps
+        R tc = m_inf<R>();
+        const R a = d[0] * d[0] + d[1] * d[1];
+        if (a > (R)0) {
+            const R b = x[0] * d[0] + x[1] * d[1];
+            const R c = x[0] * x[0] + x[1] * x[1] - s.ch_R2;
+            R disc = b * b - a * c;
+            disc = disc > (R)0 ? disc : (R)0;
+            const R sq = m_sqrt(disc);
+            R t = (b <= (R)0) ? (-b + sq) / a : -c / (b + sq);
+            tc = t > (R)0 ? t : (R)0;
+        }
+        if (d[2] > (R)0) {
+            R t = (s.zhi - x[2]) / d[2];
+            t = t > (R)0 ? t : (R)0;
+            tc = t < tc ? t : tc;
+        } else if (d[2] < (R)0) {
+            R t = (s.zlo - x[2]) / d[2];
+            t = t > (R)0 ? t : (R)0;
+            tc = t < tc ? t : tc;
+        }
+        if (tc < best) {
+            best = tc;
+            state = HIT_WALL;
+            bin = -1;
+        }
+    }
+    if (!(best <= ell)) {
+        state = HIT_NONE;
+        bin = -1;
+    }
+    t_hit = best;
+    return Hit{state, bin};
+}
+
+// Maxwellian partner velocity from one Philox block (Box-Muller).
+template <typename R> __device__ __forceinline__ void gas_velocity(const SegDev<R>& s, uint4 r, R* V)
+{
+    const R w0 = u01<R>(r.x), w1 = u01<R>(r.y), w2 = u01<R>(r.z), w3 = u01<R>(r.w);
+    const R r0 = s.vth * m_sqrt((R)-2 * m_log(w0)), r1 = s.vth * m_sqrt((R)-2 * m_log(w2));
+    R s1, c1, s3, c3;
+    m_sincos2pi(w1, &s1, &c1);
+    m_sincos2pi(w3, &s3, &c3);
+    V[0] = r0 * c1;
+    V[1] = r0 * s1;
+    V[2] = r1 * c3;
+}
+
+// Elastic binary collision with a gas atom of velocity V: new direction and energy.
+template <typename R>
+__device__ __forceinline__ void collide(const SegDev<R>& s, const TabDev<R>& tb, R& E, R* d, const R* V, R u_b,
+                                        R u_phi)
+{
+    const R v = m_sqrt(E * s.two_over_Ms);
+    const R vv[3] = {v * d[0], v * d[1], v * d[2]};
+    const R g[3] = {vv[0] - V[0], vv[1] - V[1], vv[2] - V[2]};
+    const R gm2 = dot3(g, g);
+    if (!(gm2 > (R)0)) return;                // no relative motion: nothing happens
+    const R gm = m_sqrt(gm2);
+    const R Er = s.half_mu_red * gm2;
+    const R th = tab_theta(tb, m_log2(Er) * tb.xs + s.xo_coll, m_sqrt(u_b));
+    R st, ct, sp, cp;
+    m_sincos(th, &st, &ct);
+    m_sincos2pi(u_phi, &sp, &cp);
+    const R inv = (R)1 / gm;
+    const R gu = g[0] * inv, gv = g[1] * inv, gw = g[2] * inv;
+    R n0, n1, n2;
+    if (fabs(gw) < (R)0.99999) {
+        const R rho = m_sqrt(((R)1 - gw) * ((R)1 + gw));
+        const R ir = (R)1 / rho;
+        n0 = gu * ct + st * (gu * gw * cp - gv * sp) * ir;
+        n1 = gv * ct + st * (gv * gw * cp + gu * sp) * ir;
+        n2 = gw * ct - rho * st * cp;
+    } else {
+        n0 = st * cp;
+        n1 = st * sp;
+        n2 = (gw > (R)0 ? ct : -ct);
+    }
+    const R k = s.Mg_frac * gm;
+    const R vp[3] = {s.Ms_frac * vv[0] + s.Mg_frac * V[0] + k * n0, s.Ms_frac * vv[1] + s.Mg_frac * V[1] + k * n1,
+                     s.Ms_frac * vv[2] + s.Mg_frac * V[2] + k * n2};
+    const R vp2 = dot3(vp, vp);
+    E = s.half_Ms * vp2;
+    if (vp2 > (R)0) {
+        const R iv = (R)1 / m_sqrt(vp2);
+        d[0] = vp[0] * iv;
+        d[1] = vp[1] * iv;
+        d[2] = vp[2] * iv;
+    }
+}
+
+// Isotropic direction and exponential step of a thermalised atom (sub-block 0 of the event).
+template <typename R>
+__device__ __forceinline__ R diffusive_draw(const SegDev<R>& s, uint4 r, R* d)
+{
+    const R u0 = u01<R>(r.x), u1 = u01<R>(r.y), u2 = u01<R>(r.z);
+    const R mu = (R)2 * u1 - (R)1;
+    const R st = m_sqrt(((R)1 - mu) * ((R)1 + mu));
+    R sp, cp;
+    m_sincos2pi(u2, &sp, &cp);
+    d[0] = st * cp;
+    d[1] = st * sp;
+    d[2] = mu;
+    return -s.lam_th * m_log(u0);
+}
+
+// Compensated (Kahan) accumulation: the position is s - c with c the rounding lost so far,
+// so thousands of diffusive steps do not accumulate FP32 rounding of the position.
+template <typename R> __device__ __forceinline__ void kahan_add(R& s, R& c, R v)
+{
+    const R y = v - c;
+    const R t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// Per-particle dynamic state.
+template <typename R> struct Particle {
+    R x[3], xc[3], d[3], E;   // position = x - xc (compensated)
+    uint32_t e;        // flights taken
+    uint32_t ndiff;    // diffusive steps ended in the gas
+    uint32_t ncoll;    // ballistic collisions
+    int st;            // ST_BALLISTIC / ST_DIFFUSIVE / ST_DEAD
+};
+
+struct Term {
+    int state;         // HIT_DEPOSITED / HIT_WALL / HIT_ESCAPED, HIT_NONE while alive
+    int bin;
+};
+
+// One flight of a live particle: event number p.e + 1.  Returns the terminal
+// outcome (HIT_NONE if the particle is still in the gas afterwards).
+template <typename R>
+__device__ __forceinline__ Term step(const SegDev<R>& s, const TabDev<R>& tb, uint32_t k0, uint32_t k1, uint32_t pid,
+                                     uint32_t cap, Particle<R>& p)
+{
+    if (p.e >= cap) return Term{HIT_ESCAPED, -1};
+    const uint32_t e = p.e + 1;
+    p.e = e;
+    const uint4 r = philox4x32_10(make_uint4(pid, e, s.cfgcat, 0u), k0, k1);
+    R ell;
+    if (p.st == ST_BALLISTIC) {
+        ell = s.vacuum ? m_inf<R>() : -lambda_m(s, tb, p.E) * m_log(u01<R>(r.x));
+    } else {
+        ell = s.vacuum ? m_inf<R>() : diffusive_draw(s, r, p.d);
+    }
+    R t;
+    const Hit h = hit_test(s, p.x, p.d, ell, t, e == 1u);
+    if (h.state != HIT_NONE) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) kahan_add(p.x[i], p.xc[i], t * p.d[i]);
+        return Term{h.state, h.bin};
+    }
+    if (!(ell < m_inf<R>())) return Term{HIT_ESCAPED, -1};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) kahan_add(p.x[i], p.xc[i], ell * p.d[i]);
+    if (p.st == ST_BALLISTIC) {
+        R V[3] = {(R)0, (R)0, (R)0};
+        if (s.gas_motion) gas_velocity(s, philox4x32_10(make_uint4(pid, e, s.cfgcat, 1u), k0, k1), V);
+        collide(s, tb, p.E, p.d, V, u01<R>(r.y), u01<R>(r.z));
+        ++p.ncoll;
+        if (p.E <= s.E_th) p.st = ST_DIFFUSIVE;
+    } else {
+        ++p.ndiff;
+    }
+    if (!(m_finite(p.x[0]) && m_finite(p.x[1]) && m_finite(p.x[2]) && m_finite(p.E))) return Term{HIT_ESCAPED, -1};
+    return Term{HIT_NONE, -1};
+}
+
+template <typename R>
+__device__ __forceinline__ void start(const SegDev<R>& s, uint32_t k0, uint32_t k1, uint32_t pid, Particle<R>& p)
+{
+    const uint4 r0 = philox4x32_10(make_uint4(pid, 0u, s.cfgcat, 0u), k0, k1);
+    const uint4 r1 = philox4x32_10(make_uint4(pid, 0u, s.cfgcat, 1u), k0, k1);
+    launch(s, r0, r1, p.x, p.d, p.E);
+    p.xc[0] = p.xc[1] = p.xc[2] = (R)0;
+    p.e = 0;
+    p.ndiff = 0;
+    p.ncoll = 0;
+    p.st = ST_BALLISTIC;
+}
+
+}  // namespace spx

@@ -1,0 +1,124 @@
+// spx_host.hpp -- host-side plan object and error plumbing of libspx.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/spx.h"
+#include "spx_device.hpp"
+
+namespace spx {
+
+void set_error(const std::string& msg);
+
+#define SPX_HIP(call)                                                                                   \
+    do {                                                                                                \
+        hipError_t e_ = (call);                                                                         \
+        if (e_ != hipSuccess) {                                                                         \
+            ::spx::set_error(std::string("HIP error: ") + hipGetErrorString(e_) + " at " + __FILE__ + ":" + \
+                             std::to_string(__LINE__));                                                 \
+            return SPX_EDEVICE;                                                                         \
+        }                                                                                               \
+    } while (0)
+
+#define SPX_TRY(call)                          \
+    do {                                       \
+        int r_ = (call);                       \
+        if (r_ != SPX_OK) return r_;           \
+    } while (0)
+
+// FP64 constants of one (config, cathode) segment, in the chamber frame.
+struct SegHost {
+    int cfg, cath;
+    double cat_c[3], cat_n[3], cat_u[3], cat_v[3], cat_R;
+    double sub_c[3], sub_n[3], sub_u[3], sub_v[3], half_u, half_v, du, dv;
+    int shape, nu, nv;
+    double ch_R, zlo, zhi, z_mid;
+    double rt_mu, rt_sig, PhiA, QB, dPhi;
+    double Us, Emax, smax, Lambda;
+    double Ms, Mg, mu_red, a_mm, eps_per_eV;
+    double n_mm3, kT, vth, vg, E_th, lam_th;
+    int gas_motion;
+    double pressure;
+    uint64_t N, bin_off, first_rec;
+    double cost;          // relative expected work per particle (ticket ordering)
+};
+
+// Launch arguments of the batched FP32 transport kernel.
+struct TransportArgs {
+    const SegDev<float>* segs;
+    TabDev<float> tab;
+    const uint64_t* tfirst;     // [n_seg + 1] first ticket of each position in ticket order
+    const uint32_t* torder;     // [n_seg] segment at each position
+    uint64_t* ticket;           // global ticket counter
+    unsigned long long* counts;
+    unsigned long long* counters;
+    spx_record* records;
+    uint64_t total;             // tickets
+    uint32_t k0, k1;            // Philox key (seed words)
+    uint32_t cap;
+    int32_t n_seg;
+    int32_t refill_min;
+};
+
+struct GraphKey {
+    uint64_t seed = 0;
+    void* counts = nullptr;
+    void* counters = nullptr;
+    void* profiles = nullptr;
+    void* records = nullptr;
+    int blocks = 0, threads = 0, refill = 0;
+    bool operator==(const GraphKey& o) const
+    {
+        return seed == o.seed && counts == o.counts && counters == o.counters && profiles == o.profiles &&
+               records == o.records && blocks == o.blocks && threads == o.threads && refill == o.refill;
+    }
+};
+
+}  // namespace spx
+
+struct spx_plan {
+    int device = 0;
+    spx_params params{};
+    std::vector<spx::SegHost> seg;
+    int n_seg = 0;
+    uint64_t n_bins_total = 0, n_particles_total = 0;
+    std::vector<uint64_t> h_bin_off, h_first;
+    std::vector<double> h_betamax;          // FP64 beta_max table copy (host)
+    std::vector<double> seg_norm;           // 1 / (N * bin area) per segment
+
+    hipStream_t work_stream = nullptr;
+    double* d_theta64 = nullptr;
+    double* d_betamax64 = nullptr;
+    float* d_theta32 = nullptr;
+    float* d_betamax32 = nullptr;
+    spx::SegDev<float>* d_seg32 = nullptr;
+    spx::SegDev<double>* d_seg64 = nullptr;
+    uint64_t* d_tfirst = nullptr;
+    uint32_t* d_torder = nullptr;
+    uint64_t* d_ticket = nullptr;
+    uint64_t* d_bin_off = nullptr;          // [n_seg + 1]
+    double* d_seg_norm = nullptr;           // [n_seg]
+    uint64_t n_tickets = 0;
+
+    int blocks = 0, threads = 256, refill_min = 1;
+    int max_blocks_per_cu = 0, n_cu = 0;
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    spx::GraphKey graph_key;
+};
+
+namespace spx {
+using Plan = spx_plan;
+int build_tables(Plan* P);
+int launch_transport32(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
+                       spx_record* d_records, hipStream_t st, const uint64_t* tfirst, uint64_t total,
+                       int blocks, int threads, int refill_min);
+int launch_transport64(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
+                       spx_record* d_records, hipStream_t st);
+int occupancy_transport32(int threads, int* blocks_per_cu);
+}  // namespace spx

@@ -1,0 +1,249 @@
+// transport.hip -- the two transport paths and their tally kernels.
+//
+// Batched FP32 path (k_transport32): one persistent launch covers every
+// (configuration, cathode) segment of a plan.  Each lane holds one particle in
+// registers; when lanes die the wave claims a run of tickets with a single atomic
+// (ballot + mbcnt prefix gives each dead lane its ticket), maps each ticket to
+// (segment, particle) through the prefix table, and launches the new particles.
+// Every iteration advances each live lane by one flight.  Because the random
+// numbers are keyed by (seed, segment, particle, event), the result does not depend
+// on which lane or wave ran a particle, nor on the ticket order.  Deposits go to
+// the integer tally with 64-bit atomics; per-segment counters are accumulated in
+// registers while a lane stays in one segment and flushed when it changes.
+//
+// Plain FP64 path (k_transport64): one thread per particle runs the whole history;
+// one launch per segment.  It is the comparator for the batched path.
+#include <hip/hip_runtime.h>
+
+#include "spx_host.hpp"
+
+namespace spx {
+
+__device__ __forceinline__ void add_counters(unsigned long long* C, const uint32_t* acc)
+{
+#pragma unroll
+    for (int i = 0; i < N_COUNTERS; ++i)
+        if (acc[i]) atomicAdd(&C[i], (unsigned long long)acc[i]);
+}
+
+template <typename R>
+__device__ __forceinline__ void write_record(spx_record* rec, const SegDev<R>& s, uint32_t pid, const Particle<R>& p,
+                                             const Term& t)
+{
+    spx_record r;
+    r.x = (double)p.x[0] - (double)p.xc[0];
+    r.y = (double)p.x[1] - (double)p.xc[1];
+    r.z = ((double)p.x[2] - (double)p.xc[2]) + (double)s.z_mid;
+    r.E = (double)p.E;
+    r.state = (uint32_t)t.state;
+    r.bin = t.state == HIT_DEPOSITED ? (uint32_t)t.bin : 0xFFFFFFFFu;
+    r.events = p.e;
+    r.diffusive = p.ndiff;
+    rec[s.first_rec + pid] = r;
+}
+
+__global__ void __launch_bounds__(1024) k_transport32(TransportArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    Particle<float> p;
+    p.st = ST_DEAD;
+    p.e = p.ndiff = p.ncoll = 0;
+    uint32_t pid = 0;
+    int seg = 0;
+    int acc_seg = -1;
+    uint32_t acc[N_COUNTERS] = {0, 0, 0, 0, 0, 0};
+    bool drained = false;   // wave-uniform: the ticket space is exhausted
+
+    for (;;) {
+        const uint64_t dead = __ballot(p.st == ST_DEAD);
+        const int n_dead = __popcll(dead);
+        if (!drained && n_dead > 0 && (n_dead >= a.refill_min || n_dead == 64)) {
+            const int leader = __ffsll((unsigned long long)dead) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd((unsigned long long*)a.ticket, (unsigned long long)n_dead);
+            base = __shfl(base, leader);
+            if (base + (uint64_t)n_dead >= a.total) drained = true;
+            if (p.st == ST_DEAD) {
+                const uint64_t my = base + (uint64_t)__popcll(dead & lt_mask);
+                if (my < a.total) {
+                    int lo = 0, hi = a.n_seg;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (a.tfirst[mid] <= my) lo = mid; else hi = mid;
+                    }
+                    const int sg = (int)a.torder[lo];
+                    pid = (uint32_t)(my - a.tfirst[lo]);
+                    if (sg != acc_seg) {
+                        if (acc_seg >= 0) add_counters(a.counters + (size_t)acc_seg * N_COUNTERS, acc);
+#pragma unroll
+                        for (int i = 0; i < N_COUNTERS; ++i) acc[i] = 0;
+                        acc_seg = sg;
+                    }
+                    seg = sg;
+                    start(a.segs[seg], a.k0, a.k1, pid, p);
+                    acc[C_LAUNCHED] += 1;
+                }
+            }
+        }
+        if (__ballot(p.st != ST_DEAD) == 0) {
+            if (drained) break;
+            continue;
+        }
+        if (p.st != ST_DEAD) {
+            const SegDev<float>& s = a.segs[seg];
+            const Term t = step(s, a.tab, a.k0, a.k1, pid, a.cap, p);
+            if (t.state != HIT_NONE) {
+                acc[t.state == HIT_DEPOSITED ? C_DEPOSITED : (t.state == HIT_WALL ? C_WALL : C_ESCAPED)] += 1;
+                acc[C_COLLISIONS] += p.ncoll;
+                acc[C_DIFFUSIVE] += p.ndiff;
+                if (t.state == HIT_DEPOSITED) atomicAdd(&a.counts[s.bin_off + (uint64_t)t.bin], 1ull);
+                if (a.records) write_record(a.records, s, pid, p, t);
+                p.st = ST_DEAD;
+            }
+        }
+    }
+    if (acc_seg >= 0) add_counters(a.counters + (size_t)acc_seg * N_COUNTERS, acc);
+}
+
+__global__ void __launch_bounds__(256) k_transport64(const SegDev<double>* __restrict__ segp, TabDev<double> tab,
+                                                     uint32_t k0, uint32_t k1, uint32_t cap,
+                                                     unsigned long long* __restrict__ counts,
+                                                     unsigned long long* __restrict__ counters,
+                                                     spx_record* __restrict__ records)
+{
+    const SegDev<double>& s = *segp;
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc[N_COUNTERS] = {0, 0, 0, 0, 0, 0};
+    if (i < s.N) {
+        const uint32_t pid = (uint32_t)i;
+        Particle<double> p;
+        start(s, k0, k1, pid, p);
+        Term t;
+        do {
+            t = step(s, tab, k0, k1, pid, cap, p);
+        } while (t.state == HIT_NONE);
+        acc[C_LAUNCHED] = 1;
+        acc[t.state == HIT_DEPOSITED ? C_DEPOSITED : (t.state == HIT_WALL ? C_WALL : C_ESCAPED)] = 1;
+        acc[C_COLLISIONS] = p.ncoll;
+        acc[C_DIFFUSIVE] = p.ndiff;
+        if (t.state == HIT_DEPOSITED) atomicAdd(&counts[s.bin_off + (uint64_t)t.bin], 1ull);
+        if (records) write_record(records, s, pid, p, t);
+    }
+    // wave sum of the counters, one atomic per counter and wave
+#pragma unroll
+    for (int c = 0; c < N_COUNTERS; ++c) {
+        unsigned long long v = acc[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if ((threadIdx.x & 63) == 0 && v) atomicAdd(&counters[c], v);
+    }
+}
+
+// Zero the outputs and the ticket counter (a kernel, so that it can sit in a graph).
+__global__ void k_zero(unsigned long long* counts, uint64_t n_counts, unsigned long long* counters, uint64_t n_counters,
+                       uint64_t* ticket)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_counts; i += stride) counts[i] = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_counters; i += stride) counters[i] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && ticket) *ticket = 0;
+}
+
+// profiles = counts / (N_seg * bin area); FP64.
+__global__ void k_normalize(const unsigned long long* __restrict__ counts, const uint64_t* __restrict__ bin_off,
+                            const double* __restrict__ seg_norm, int n_seg, uint64_t n_bins,
+                            double* __restrict__ profiles)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_bins; b += stride) {
+        int lo = 0, hi = n_seg;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (bin_off[mid] <= b) lo = mid; else hi = mid;
+        }
+        profiles[b] = (double)counts[b] * seg_norm[lo];
+    }
+}
+
+static int launch_zero_and_tail(Plan* P, uint64_t* d_counts, uint64_t* d_counters, uint64_t* ticket, hipStream_t st)
+{
+    const uint64_t n = P->n_bins_total;
+    const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 + 1 : 4096);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, (unsigned long long*)d_counts, n,
+                       (unsigned long long*)d_counters, (uint64_t)P->n_seg * N_COUNTERS, ticket);
+    SPX_HIP(hipGetLastError());
+    return SPX_OK;
+}
+
+static int launch_normalize(Plan* P, const uint64_t* d_counts, double* d_profiles, hipStream_t st)
+{
+    const uint64_t n = P->n_bins_total;
+    const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 + 1 : 4096);
+    hipLaunchKernelGGL(k_normalize, dim3(blocks), dim3(256), 0, st, (const unsigned long long*)d_counts,
+                       P->d_bin_off, P->d_seg_norm, P->n_seg, n, d_profiles);
+    SPX_HIP(hipGetLastError());
+    return SPX_OK;
+}
+
+int occupancy_transport32(int threads, int* blocks_per_cu)
+{
+    SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_transport32, threads, 0));
+    return SPX_OK;
+}
+
+int launch_transport32(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
+                       spx_record* d_records, hipStream_t st, const uint64_t* tfirst, uint64_t total, int blocks,
+                       int threads, int refill_min)
+{
+    SPX_TRY(launch_zero_and_tail(P, d_counts, d_counters, P->d_ticket, st));
+    TransportArgs a;
+    a.segs = P->d_seg32;
+    a.tab.theta = P->d_theta32;
+    a.tab.betamax = P->d_betamax32;
+    a.tab.ne = P->params.table_ne;
+    a.tab.ns = P->params.table_ns;
+    a.tab.xs = (float)((P->params.table_ne - 1) / ((P->params.log_eps_hi - P->params.log_eps_lo) * 3.321928094887362));
+    a.tfirst = tfirst;
+    a.torder = P->d_torder;
+    a.ticket = P->d_ticket;
+    a.counts = (unsigned long long*)d_counts;
+    a.counters = (unsigned long long*)d_counters;
+    a.records = d_records;
+    a.total = total;
+    a.k0 = (uint32_t)seed;
+    a.k1 = (uint32_t)(seed >> 32);
+    a.cap = P->params.event_cap;
+    a.n_seg = P->n_seg;
+    a.refill_min = refill_min;
+    hipLaunchKernelGGL(k_transport32, dim3(blocks), dim3(threads), 0, st, a);
+    SPX_HIP(hipGetLastError());
+    if (d_profiles) SPX_TRY(launch_normalize(P, d_counts, d_profiles, st));
+    return SPX_OK;
+}
+
+int launch_transport64(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
+                       spx_record* d_records, hipStream_t st)
+{
+    SPX_TRY(launch_zero_and_tail(P, d_counts, d_counters, nullptr, st));
+    TabDev<double> tab;
+    tab.theta = P->d_theta64;
+    tab.betamax = P->d_betamax64;
+    tab.ne = P->params.table_ne;
+    tab.ns = P->params.table_ns;
+    tab.xs = (P->params.table_ne - 1) / ((P->params.log_eps_hi - P->params.log_eps_lo) * 3.321928094887362);
+    for (int k = 0; k < P->n_seg; ++k) {
+        const uint64_t N = P->seg[k].N;
+        if (N == 0) continue;
+        const uint64_t blocks = (N + 255) / 256;
+        hipLaunchKernelGGL(k_transport64, dim3((unsigned)blocks), dim3(256), 0, st, P->d_seg64 + k, tab,
+                           (uint32_t)seed, (uint32_t)(seed >> 32), P->params.event_cap,
+                           (unsigned long long*)d_counts, (unsigned long long*)(d_counters + (size_t)k * N_COUNTERS),
+                           d_records);
+        SPX_HIP(hipGetLastError());
+    }
+    if (d_profiles) SPX_TRY(launch_normalize(P, d_counts, d_profiles, st));
+    return SPX_OK;
+}
+
+}  // namespace spx

@@ -1,0 +1,95 @@
+"""The C-ABI library: it loads, exports every symbol include/spx.h declares, and its
+host-side validation rejects bad inputs before touching a device (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import sputter_inputs as si
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "spx.h")).read()
+    return sorted(set(re.findall(r"\b(spx_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2411_14413_amd import _native
+    L = _native.lib()
+    declared = _declared()
+    assert len(declared) >= 18
+    for name in declared:
+        assert hasattr(L, name), name
+    # the binding knows the same set
+    assert set(declared) == set(_native.SIGNATURES)
+    assert L.spx_version() >= 100
+
+
+def test_header_struct_sizes_match_binding():
+    from paper_2411_14413_amd import _native as N
+    assert ctypes.sizeof(N.Record) == 48
+    assert ctypes.sizeof(N.Cathode) == 8 * (9 + 1 + 4 + 4) + 8 + 8 * 6 + 8
+    assert ctypes.sizeof(N.Chamber) == 8 * 6 + 8
+    assert ctypes.sizeof(N.Grid) == 8 * 11 + 16
+
+
+def _create(cfgs, **kw):
+    import paper_2411_14413_amd as spx
+    return spx.Plan(cfgs, si.Params(**kw))
+
+
+@pytest.mark.parametrize("mutate, msg", [
+    (lambda c: setattr(c.chamber, "pressure", -1.0), "pressure"),
+    (lambda c: setattr(c.chamber, "T", 0.0), "temperature"),
+    (lambda c: setattr(c.cathodes[0], "n_particles", 0), "n_particles"),
+    (lambda c: setattr(c.cathodes[0], "rt_lo", 30.0), "racetrack"),
+    (lambda c: setattr(c.cathodes[0], "mass", -1.0), "mass"),
+    (lambda c: setattr(c.cathodes[0], "E_i", 1.0), "E_max"),
+    (lambda c: setattr(c.cathodes[0], "cos_coeff", (0.5, 0.5, 0, 0, 0, 0)), "cosine"),
+    (lambda c: setattr(c.cathodes[0], "center", (190.0, 0.0, 100.0)), "outside"),
+    (lambda c: setattr(c.grid, "nu", 0), "nu"),
+    (lambda c: setattr(c.grid, "normal", (0.0, 0.0, -2.0)), "orthonormal"),
+    (lambda c: setattr(c, "cathodes", []), "cathodes"),
+])
+def test_validation_rejects_bad_configs(mutate, msg):
+    from paper_2411_14413_amd import SpxError
+    cfg = si.single_ni(0.5, 100)
+    mutate(cfg)
+    with pytest.raises(SpxError) as e:
+        _create([cfg])
+    assert e.value.code == -1
+    assert msg.lower() in str(e.value).lower()
+
+
+def test_validation_rejects_bad_params():
+    from paper_2411_14413_amd import SpxError
+    for kw in (dict(theta_min=0.0), dict(table_ne=1), dict(log_eps_lo=0.0, log_eps_hi=-1.0), dict(E_th_kT=-1.0)):
+        with pytest.raises(SpxError) as e:
+            _create([si.single_ni(0.5, 10)], **kw)
+        assert e.value.code == -1
+
+
+def test_area_centres_host_entry_point():
+    import numpy as np
+
+    import paper_2411_14413_amd as spx
+    c = spx.area_centres(342, 4.5)
+    assert c.shape == (342, 2)
+    r = np.hypot(c[:, 0], c[:, 1])
+    assert np.all(np.diff(r) >= -1e-12)
+    from paper_2411_14413_amd import SpxError
+    with pytest.raises(SpxError):
+        spx.area_centres(0, 4.5)
+
+
+def test_valid_config_without_device_is_a_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2411_14413_amd import SpxError
+    with pytest.raises(SpxError) as e:
+        _create([si.single_ni(0.5, 10)])
+    assert e.value.code == -3

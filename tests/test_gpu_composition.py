@@ -1,0 +1,173 @@
+"""GPU parity of the post-processing path: area average, composition map forward and
+hand-written backward, squared Euclidean distance, and their use for power
+inversion and power-rate fitting.  References: the oracle's float64 numpy forward
+and float64 torch-autograd gradients on the CPU, and central finite differences.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import sputter_inputs as si
+from parity import say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2411_14413_amd as spx  # noqa: E402
+
+PARAMS = si.Params()
+
+
+def _inputs(B=64, J=342, K=4, seed=0):
+    ci = si.composition_inputs(batch=B)
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(0.02, 0.2, (K, J)) * (1.0 + 0.5 * np.sin(np.linspace(0, 3, J)))[None, :]
+    fref = f.mean(axis=1)
+    return f, ci.a, ci.b, ci.P, ci.M, ci.rho, fref
+
+
+def _cuda(*xs):
+    return [torch.as_tensor(np.asarray(x), dtype=torch.float32, device="cuda").contiguous() for x in xs]
+
+
+def test_area_centres_match_oracle():
+    assert np.array_equal(spx.area_centres(342, 4.5), oracle.area_centres(342, 4.5))
+    assert np.array_equal(spx.area_centres(57, 3.0), oracle.area_centres(57, 3.0))
+
+
+def test_area_gather_matches_oracle():
+    g = si.quaternary().grid
+    rng = np.random.default_rng(1)
+    prof = rng.uniform(0, 1e-3, (3, g.nv, g.nu))
+    cen = oracle.area_centres()
+    got = spx.area_gather(torch.as_tensor(prof, device="cuda"), g, cen).cpu().numpy()
+    for p in range(3):
+        ref = oracle.area_gather(prof[p], g, cen)
+        assert np.allclose(got[p], ref, rtol=1e-13, atol=0)
+    # a coarse grid and a rectangle
+    g2 = si.Grid(nu=50, nv=40, half_u=50.0, half_v=40.0)
+    prof2 = rng.uniform(0, 1, (40, 50))
+    cen2 = np.array([[0.0, 0.0], [12.3, -7.7], [-48.0, 38.5]])
+    assert np.allclose(spx.area_gather(torch.as_tensor(prof2, device="cuda"), g2, cen2).cpu().numpy()[0],
+                       oracle.area_gather(prof2, g2, cen2), rtol=1e-13)
+
+
+@pytest.mark.parametrize("B,J,K", [(1024, 342, 4), (3, 5, 1), (7, 1000, 3), (300, 1, 16)])
+def test_forward_matches_oracle(B, J, K):
+    say(f"composition forward B={B} J={J} K={K}")
+    rng = np.random.default_rng(B + J + K)
+    f = rng.uniform(0.01, 1.0, (K, J))
+    a, b = rng.uniform(0.5, 2, K), rng.uniform(0, 0.2, K)
+    P = rng.uniform(20, 200, (B, K))
+    M, rho = rng.uniform(50, 200, K), rng.uniform(8, 22, K)
+    fref = f.mean(axis=1)
+    ref = oracle.composition(f, a, b, P, M, rho, fref)
+    got = spx.comp_forward(*_cuda(f, a, b, P, M, rho, fref)).cpu().numpy()
+    assert got.shape == (B, J, K)
+    assert np.abs(got - ref).max() < 2e-4          # at.%, FP32
+    assert np.abs(got.sum(axis=2) - 100).max() < 2e-4
+
+
+def test_backward_matches_autograd_reference():
+    f, a, b, P, M, rho, fref = _inputs(B=256)
+    ct = oracle.composition(f, a, b, P[:1] * 1.05, M, rho, fref)[0] + 0.2
+    ref = oracle.composition_grads(f, a, b, P, M, rho, fref, ct[None])
+    dev = _cuda(f, a, b, P, M, rho, fref)
+    for t in dev:
+        t.requires_grad_(True)
+    c = spx.CompositionMap.apply(*dev)
+    loss = spx.SquaredDistance.apply(c, torch.as_tensor(ct, dtype=torch.float32, device="cuda")).sum()
+    loss.backward()
+    assert abs(float(loss) / ref["loss"] - 1) < 1e-4
+    for name, t in zip(("f", "a", "b", "P", "M", "rho", "fref"), dev):
+        g = t.grad.cpu().numpy().astype(np.float64)
+        r = ref[name]
+        scale = np.abs(r).max()
+        err = np.abs(g - r).max() / scale
+        say(f"  grad {name}: rel err {err:.2e}")
+        assert err < 2e-4, (name, err)
+
+
+def test_backward_finite_differences():
+    # central differences of the GPU forward itself, in float64 inputs rounded to FP32
+    f, a, b, P, M, rho, fref = _inputs(B=4, J=12, K=3)
+    gc = np.random.default_rng(5).normal(size=(4, 12, 3))
+    g = spx.comp_backward(*_cuda(f, a, b, P, M, rho, fref, gc))
+    L = lambda **kw: float((spx.comp_forward(*_cuda(*[kw.get(n, v) for n, v in zip(
+        ("f", "a", "b", "P", "M", "rho", "fref"), (f, a, b, P, M, rho, fref))])).double().cpu().numpy() * gc).sum())
+    for name, base in zip(("a", "b", "M", "rho", "fref"), (a, b, M, rho, fref)):
+        for i in range(len(base)):
+            h = 1e-2 * abs(base[i]) + 1e-3
+            xp, xm = base.copy(), base.copy()
+            xp[i] += h
+            xm[i] -= h
+            fd = (L(**{name: xp}) - L(**{name: xm})) / (2 * h)
+            an = float(g[name][i])
+            assert abs(fd - an) <= 2e-2 * max(abs(fd), 1e-2), (name, i, fd, an)
+
+
+def test_sqdist_kernel():
+    c = np.random.default_rng(0).uniform(0, 100, (5, 9, 4))
+    ct = np.random.default_rng(1).uniform(0, 100, (9, 4))
+    loss, gc = spx.comp_sqdist(*_cuda(c, ct), want_grad=True)
+    assert np.allclose(loss.cpu().numpy(), ((c - ct[None]) ** 2).sum(axis=(1, 2)), rtol=1e-5)
+    assert np.allclose(gc.cpu().numpy(), 2 * (c - ct[None]), rtol=1e-5, atol=1e-4)
+    # d_e in % of the largest quaternary distance sqrt(2) * 100 at.%: pure elements are 100 % apart
+    pure = np.zeros((1, 1, 4)); pure[0, 0, 0] = 100.0
+    other = np.zeros((1, 4)); other[0, 1] = 100.0
+    l = spx.comp_sqdist(*_cuda(pure, other)).cpu().numpy()
+    assert abs(np.sqrt(l[0]) / np.sqrt(2) - 100.0) < 1e-4
+
+
+def test_power_inversion_recovers_planted_powers():
+    """Invert for the cathode powers that reproduce a target composition map."""
+    f, a, b, P, M, rho, fref = _inputs(B=64)
+    P_star = np.array([[60.0, 25.0, 90.0, 140.0]])
+    ct = oracle.composition(f, a, b, P_star, M, rho, fref)[0]
+    fa, aa, ba, _, Ma, ra, fra = _cuda(f, a, b, P, M, rho, fref)
+    ctt = torch.as_tensor(ct, dtype=torch.float32, device="cuda")
+    # 64 random starts in U(20, 200) optimised together in log-power
+    logP = torch.log(torch.as_tensor(P, dtype=torch.float32, device="cuda")).requires_grad_(True)
+    opt = torch.optim.Adam([logP], lr=0.05)
+    for it in range(600):
+        opt.zero_grad()
+        c = spx.CompositionMap.apply(fa, aa, ba, torch.exp(logP), Ma, ra, fra)
+        loss = spx.SquaredDistance.apply(c, ctt).sum()
+        loss.backward()
+        opt.step()
+    Pf = torch.exp(logP).detach().cpu().numpy()
+    # compositions depend on power ratios only up to the rate offsets b: compare maps
+    cf = oracle.composition(f, a, b, Pf.astype(np.float64), M, rho, fref)
+    de = np.sqrt(((cf - ct[None]) ** 2).sum(axis=2)).mean(axis=1)
+    say(f"  inversion: median mean-d_e {np.median(de):.2e} at.%")
+    assert np.median(de) < 0.05
+
+
+def test_power_rate_fit_from_compositions():
+    """Fit a and b of the rate model to compositions produced by planted (a*, b*)."""
+    f, a, b, P, M, rho, fref = _inputs(B=128)
+    a_star = np.array([1.2, 0.7, 1.9, 0.9])
+    b_star = np.array([0.05, 0.15, 0.02, 0.1])
+    ct = oracle.composition(f, a_star, b_star, P, M, rho, fref)
+    fa, _, _, Pa, Ma, ra, fra = _cuda(f, a, b, P, M, rho, fref)
+    ctt = torch.as_tensor(ct, dtype=torch.float32, device="cuda")
+    # compositions fix the rates only up to a common factor: pin a[0] = a*[0]
+    la = torch.zeros(4, device="cuda", requires_grad=True)
+    lb = torch.full((4,), -3.0, device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([la, lb], lr=0.03)
+    for it in range(2000):
+        opt.zero_grad()
+        aa = float(a_star[0]) * torch.exp(la - la[0])
+        bb = torch.exp(lb)
+        c = spx.CompositionMap.apply(fa, aa, bb, Pa, Ma, ra, fra)
+        loss = spx.SquaredDistance.apply(c, ctt).mean()
+        loss.backward()
+        opt.step()
+    aa = (float(a_star[0]) * torch.exp(la - la[0])).detach().cpu().numpy()
+    bb = torch.exp(lb).detach().cpu().numpy()
+    say(f"  fit: a={aa}, b={bb}, loss={float(loss):.3e}")
+    assert np.allclose(aa, a_star, rtol=2e-2)
+    assert np.allclose(bb, b_star, rtol=0.1, atol=5e-3)
