@@ -56,7 +56,8 @@ extern "C" {
 #define SPX_C_ESCAPED 3
 #define SPX_C_COLLISIONS 4      /* ballistic flights that ended in a gas collision */
 #define SPX_C_DIFFUSIVE 5       /* diffusive steps that ended in the gas */
-#define SPX_N_COUNTERS 6
+#define SPX_C_THERMALIZED 6     /* particles that reached the diffusive (thermalised) state */
+#define SPX_N_COUNTERS 7
 
 /* Magnetron cathode: planar circular target (Methods, "The SIMTRA Python wrapper": the
  * magnetron object holds the element, the racetrack and the geometry). */

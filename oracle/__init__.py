@@ -35,7 +35,7 @@ SEG_LEN = 48
 P_LEN = 8
 REC = 8
 STATE_DEPOSITED, STATE_WALL, STATE_ESCAPED = 1, 2, 3
-COUNTER_NAMES = ("launched", "deposited", "wall", "escaped", "collisions", "diffusive_steps")
+COUNTER_NAMES = ("launched", "deposited", "wall", "escaped", "collisions", "diffusive_steps", "thermalized")
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -293,7 +293,7 @@ def run(cfgs, params, seed: int, pid_begin: int = 0, pid_end: int = None, n_thre
     """Simulate particles [pid_begin, pid_end) of every (config, cathode).
 
     Returns ``counts`` (list of [nv, nu] uint64 arrays, one per segment),
-    ``counters`` ([n_seg, 6] uint64, order COUNTER_NAMES), ``records``
+    ``counters`` ([n_seg, 7] uint64, order COUNTER_NAMES), ``records``
     ([n, 8] float64: x, y, z, state, bin, events, diffusive steps, final E) and
     ``threads`` (OpenMP threads used)."""
     S, prm, th, bm = _args(cfgs, params)
@@ -303,7 +303,7 @@ def run(cfgs, params, seed: int, pid_begin: int = 0, pid_end: int = None, n_thre
     if pid_end is None:
         pid_end = 1 << 62
     counts = np.zeros(n_bins, dtype=np.uint64)
-    counters = np.zeros((n_seg, 6), dtype=np.uint64)
+    counters = np.zeros((n_seg, len(COUNTER_NAMES)), dtype=np.uint64)
     n_rec = sum(max(0, min(int(S[k, 43]), pid_end) - pid_begin) for k in range(n_seg))
     rec = np.zeros((n_rec, REC)) if records else None
     used = lib().or_run(_p(S), n_seg, _p(prm), _p(th), _p(bm), seed, pid_begin, pid_end, n_threads,

@@ -48,7 +48,7 @@
 /* Terminal states. */
 enum { OR_ALIVE = 0, OR_DEPOSITED = 1, OR_WALL = 2, OR_ESCAPED = 3 };
 /* Counters per (config, cathode). */
-enum { OC_LAUNCHED = 0, OC_DEPOSITED, OC_WALL, OC_ESCAPED, OC_COLLISIONS, OC_DIFFSTEPS, OC_N };
+enum { OC_LAUNCHED = 0, OC_DEPOSITED, OC_WALL, OC_ESCAPED, OC_COLLISIONS, OC_DIFFSTEPS, OC_THERMALIZED, OC_N };
 
 /* ------------------------------------------------------------------------- */
 /* Philox4x32-10                                                              */
@@ -636,6 +636,7 @@ typedef struct {
     double x[3], E;
     int state, bin;
     uint32_t events, ndiff, ncoll;
+    int thermalized;
 } result_t;
 
 static int finite3(const double x[3]) { return isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]); }
@@ -688,6 +689,7 @@ static void trace(const seg_t* s, const tab_t* tb, uint64_t seed, uint32_t pid, 
     res->events = e;
     res->ndiff = ndiff;
     res->ncoll = ncoll;
+    res->thermalized = diffusive;
 }
 
 static void make_tab(const double* prm, const double* theta, const double* betamax, tab_t* tb)
@@ -714,7 +716,7 @@ static void write_record(double* rec, const result_t* r)
 
 /*
  * Run particles [pid_begin, min(pid_end, N)) of every segment.  counts (u64) is
- * indexed by seg.bin_off + bin; counters is [n_seg][6]; records (nullable) holds
+ * indexed by seg.bin_off + bin; counters is [n_seg][7]; records (nullable) holds
  * OR_REC doubles per particle in segment-major order over the simulated range.
  * Returns the number of OpenMP threads used.
  */
@@ -753,6 +755,7 @@ int or_run(const double* segs, int n_seg, const double* prm, const double* theta
                                1, __ATOMIC_RELAXED);
             __atomic_fetch_add(&C[OC_COLLISIONS], r.ncoll, __ATOMIC_RELAXED);
             __atomic_fetch_add(&C[OC_DIFFSTEPS], r.ndiff, __ATOMIC_RELAXED);
+            __atomic_fetch_add(&C[OC_THERMALIZED], (uint64_t)r.thermalized, __ATOMIC_RELAXED);
             if (r.state == OR_DEPOSITED) __atomic_fetch_add(&counts[S[k].bin_off + (uint64_t)r.bin], 1, __ATOMIC_RELAXED);
             if (records) write_record(records + (size_t)g * OR_REC, &r);
         }

@@ -52,7 +52,7 @@ __global__ void __launch_bounds__(1024) k_transport32(TransportArgs a)
     uint32_t pid = 0;
     int seg = 0;
     int acc_seg = -1;
-    uint32_t acc[N_COUNTERS] = {0, 0, 0, 0, 0, 0};
+    uint32_t acc[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0};
     bool drained = false;   // wave-uniform: the ticket space is exhausted
 
     for (;;) {
@@ -97,6 +97,7 @@ __global__ void __launch_bounds__(1024) k_transport32(TransportArgs a)
                 acc[t.state == HIT_DEPOSITED ? C_DEPOSITED : (t.state == HIT_WALL ? C_WALL : C_ESCAPED)] += 1;
                 acc[C_COLLISIONS] += p.ncoll;
                 acc[C_DIFFUSIVE] += p.ndiff;
+                acc[C_THERMALIZED] += (p.st == ST_DIFFUSIVE) ? 1u : 0u;
                 if (t.state == HIT_DEPOSITED) atomicAdd(&a.counts[s.bin_off + (uint64_t)t.bin], 1ull);
                 if (a.records) write_record(a.records, s, pid, p, t);
                 p.st = ST_DEAD;
@@ -114,7 +115,7 @@ __global__ void __launch_bounds__(256) k_transport64(const SegDev<double>* __res
 {
     const SegDev<double>& s = *segp;
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t acc[N_COUNTERS] = {0, 0, 0, 0, 0, 0};
+    uint32_t acc[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0};
     if (i < s.N) {
         const uint32_t pid = (uint32_t)i;
         Particle<double> p;
@@ -127,6 +128,7 @@ __global__ void __launch_bounds__(256) k_transport64(const SegDev<double>* __res
         acc[t.state == HIT_DEPOSITED ? C_DEPOSITED : (t.state == HIT_WALL ? C_WALL : C_ESCAPED)] = 1;
         acc[C_COLLISIONS] = p.ncoll;
         acc[C_DIFFUSIVE] = p.ndiff;
+        acc[C_THERMALIZED] = (p.st == ST_DIFFUSIVE) ? 1u : 0u;
         if (t.state == HIT_DEPOSITED) atomicAdd(&counts[s.bin_off + (uint64_t)t.bin], 1ull);
         if (records) write_record(records, s, pid, p, t);
     }

@@ -26,7 +26,7 @@ def _inputs(B=64, J=342, K=4, seed=0):
     rng = np.random.default_rng(seed)
     f = rng.uniform(0.02, 0.2, (K, J)) * (1.0 + 0.5 * np.sin(np.linspace(0, 3, J)))[None, :]
     fref = f.mean(axis=1)
-    return f, ci.a, ci.b, ci.P, ci.M, ci.rho, fref
+    return f, ci.a[:K], ci.b[:K], ci.P[:, :K], ci.M[:K], ci.rho[:K], fref
 
 
 def _cuda(*xs):
@@ -81,7 +81,7 @@ def test_backward_matches_autograd_reference():
     c = spx.CompositionMap.apply(*dev)
     loss = spx.SquaredDistance.apply(c, torch.as_tensor(ct, dtype=torch.float32, device="cuda")).sum()
     loss.backward()
-    assert abs(float(loss) / ref["loss"] - 1) < 1e-4
+    assert abs(float(loss.detach()) / ref["loss"] - 1) < 1e-4
     for name, t in zip(("f", "a", "b", "P", "M", "rho", "fref"), dev):
         g = t.grad.cpu().numpy().astype(np.float64)
         r = ref[name]
@@ -150,13 +150,13 @@ def test_power_rate_fit_from_compositions():
     """Fit a and b of the rate model to compositions produced by planted (a*, b*)."""
     f, a, b, P, M, rho, fref = _inputs(B=128)
     a_star = np.array([1.2, 0.7, 1.9, 0.9])
-    b_star = np.array([0.05, 0.15, 0.02, 0.1])
+    b_star = np.array([30.0, 12.0, 55.0, 20.0])    # offsets comparable to a P: identifiable
     ct = oracle.composition(f, a_star, b_star, P, M, rho, fref)
     fa, _, _, Pa, Ma, ra, fra = _cuda(f, a, b, P, M, rho, fref)
     ctt = torch.as_tensor(ct, dtype=torch.float32, device="cuda")
     # compositions fix the rates only up to a common factor: pin a[0] = a*[0]
     la = torch.zeros(4, device="cuda", requires_grad=True)
-    lb = torch.full((4,), -3.0, device="cuda", requires_grad=True)
+    lb = torch.full((4,), 3.0, device="cuda", requires_grad=True)
     opt = torch.optim.Adam([la, lb], lr=0.03)
     for it in range(2000):
         opt.zero_grad()
@@ -170,4 +170,4 @@ def test_power_rate_fit_from_compositions():
     bb = torch.exp(lb).detach().cpu().numpy()
     say(f"  fit: a={aa}, b={bb}, loss={float(loss):.3e}")
     assert np.allclose(aa, a_star, rtol=2e-2)
-    assert np.allclose(bb, b_star, rtol=0.1, atol=5e-3)
+    assert np.allclose(bb, b_star, rtol=3e-2)

@@ -1,0 +1,136 @@
+"""Full-size runs in the benchmark's launch configuration (autotuned), checked where
+the oracle can follow: sampled particles one by one, exact integer identities at
+every size, the analytic 0 Pa profile, and compositions against the oracle run on
+the same particles.
+
+* three 1e7-particle chambers of the single-target geometry (0.5 / 0 / 2 Pa);
+* the four-cathode Ni/Pd/Pt/Ru system, 2.3e7 particles, 200x200 wafer grid;
+* the 64-chamber sweep of that system (~1.4e8 particles) in one launch.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import sputter_inputs as si
+from parity import match_stats, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2411_14413_amd as spx  # noqa: E402
+
+PARAMS = si.Params()
+
+
+def _run_full(cfgs, seed):
+    plan = spx.Plan(cfgs, PARAMS)
+    launch = plan.autotune()
+    say(f"  launch {launch}, {plan.n_particles} particles, {plan.n_segments} segments")
+    out = plan.run(seed=seed, records=True)
+    torch.cuda.synchronize()
+    return plan, out
+
+
+def _check_integer_identities(plan, out):
+    """Tallies = histogram of the records (on the GPU), counters = record sums, conservation."""
+    rec32 = out["records"].view(torch.int32).view(-1, 12)
+    st, bn, dif = rec32[:, 8], rec32[:, 9], rec32[:, 11]
+    C = out["counters"].cpu().numpy()
+    first = list(plan.first) + [plan.n_particles]
+    for k in range(plan.n_segments):
+        a, b = first[k], first[k + 1]
+        s = st[a:b]
+        dep = s == 1
+        nb = plan.shapes[k][0] * plan.shapes[k][1]
+        h = torch.bincount(bn[a:b][dep].long(), minlength=nb)
+        assert torch.equal(h, out["counts_seg"][k].reshape(-1)), k
+        assert C[k, 0] == b - a == plan.seg_particles[k]
+        assert C[k, 1] == int(dep.sum()) and C[k, 2] == int((s == 2).sum()) and C[k, 3] == int((s == 3).sum())
+        assert C[k, 5] == int(dif[a:b].to(torch.int64).sum())
+    assert np.array_equal(C[:, 0], C[:, 1] + C[:, 2] + C[:, 3])
+
+
+def _sampled_parity(plan, out, cfgs, seed, per_seg, rng):
+    first = list(plan.first)
+    seg_ids, pids = [], []
+    for k, N in enumerate(plan.seg_particles):
+        if N == 0:
+            continue
+        p = rng.choice(N, size=min(per_seg, N), replace=False)
+        seg_ids += [k] * len(p)
+        pids += list(p)
+    seg_ids, pids = np.array(seg_ids), np.array(pids)
+    ref = oracle.run_list(cfgs, PARAMS, seed, seg_ids, pids)
+    idx = torch.as_tensor(np.array(first)[seg_ids] + pids, device="cuda")
+    rec = spx.records_to_numpy(out["records"].view(-1, 48)[idx].reshape(-1))
+    m = match_stats(rec, ref, 1e-3)
+    per = []
+    for k in np.unique(seg_ids):
+        sel = seg_ids == k
+        per.append(match_stats(rec[sel], ref[sel], 1e-3)["frac"])
+    return m, np.array(per)
+
+
+def test_fullsize_single_target_legs():
+    say("full size: 3 x 1e7, single target, 0.5 / 0 / 2 Pa")
+    cfgs = si.single_ni_legs(10_000_000)
+    plan, out = _run_full(cfgs, seed=0)
+    _check_integer_identities(plan, out)
+    m, per = _sampled_parity(plan, out, cfgs, 0, 300, np.random.default_rng(0))
+    say(f"  sampled parity {m}, per leg {per}")
+    assert m["frac"] >= 0.99 and per.min() >= 0.97
+    # the 0 Pa leg against the analytic line-of-sight profile
+    from test_oracle_transport import analytic_bin_fractions
+    counts = out["counts_seg"][1].cpu().numpy().astype(np.float64)
+    exp = 1e7 * analytic_bin_fractions(cfgs[1])
+    z = (counts - exp) / np.sqrt(exp)
+    assert (z**2).sum() < z.size + 4.5 * math.sqrt(2 * z.size) and np.abs(z).max() < 5.0
+
+
+def test_fullsize_quaternary_compositions():
+    say("full size: four cathodes, 2.3e7 particles; compositions vs the oracle on the same particles")
+    cfg = si.quaternary()
+    plan, out = _run_full([cfg], seed=1)
+    _check_integer_identities(plan, out)
+    m, per = _sampled_parity(plan, out, [cfg], 1, 400, np.random.default_rng(1))
+    say(f"  sampled parity {m}, per cathode {per}")
+    assert m["frac"] >= 0.99 and per.min() >= 0.97
+    # GPU chain: profiles -> 342 areas -> at.% for 16 power vectors
+    g = cfg.grid
+    cen = spx.area_centres(342, 4.5)
+    prof = torch.stack([p for p in out["profiles_seg"]])
+    f_gpu = spx.area_gather(prof, g, cen)                           # [4, 342] float64
+    ci = si.composition_inputs(batch=16)
+    fref = f_gpu.mean(dim=1)
+    c_gpu = spx.comp_forward(f_gpu, *[torch.as_tensor(x, device="cuda") for x in (ci.a, ci.b, ci.P, ci.M, ci.rho)],
+                             fref).cpu().numpy()
+    # oracle chain on the same particles
+    say("  oracle: 2.3e7 particles")
+    r = oracle.run([cfg], PARAMS, seed=1)
+    f_or = np.stack([oracle.area_gather(oracle.normalize(r["counts"][k], cfg.cathodes[k].n_particles, g), g,
+                                        oracle.area_centres()) for k in range(4)])
+    c_or = oracle.composition(f_or, ci.a, ci.b, ci.P, ci.M, ci.rho, f_or.mean(axis=1))
+    err = np.abs(c_gpu - c_or).max()
+    say(f"  composition max |diff| = {err:.4f} at.%")
+    assert err < 0.1
+    # tallies within counting noise of the oracle's
+    for k in range(4):
+        a = out["counts_seg"][k].cpu().numpy().astype(np.float64)
+        b = r["counts"][k].astype(np.float64)
+        z = (a - b) / np.sqrt(np.maximum(a + b, 1.0))
+        assert np.abs(z).max() < 3.0
+
+
+def test_fullsize_sweep():
+    cfgs = si.quaternary_sweep(64)
+    say(f"full size: 64-chamber sweep, {si.total_particles(cfgs)} particles in one launch")
+    plan, out = _run_full(cfgs, seed=2)
+    _check_integer_identities(plan, out)
+    m, per = _sampled_parity(plan, out, cfgs, 2, 40, np.random.default_rng(2))
+    say(f"  sampled parity {m}, worst segment {per.min()}")
+    assert m["frac"] >= 0.99 and per.min() >= 0.9

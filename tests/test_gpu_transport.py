@@ -111,6 +111,8 @@ def test_per_particle_parity(batch_ref, precision, tol, need):
         assert C[k, 3] == (r["state"] == 3).sum()
         assert C[k, 5] == r["diffusive"].astype(np.int64).sum()
         assert C[k, 0] == C[k, 1] + C[k, 2] + C[k, 3]
+        assert abs(int(C[k, 6]) - int(ref["counters"][k, 6])) <= 0.01 * C[k, 0] + 3
+        assert int(C[k, 6]) >= int((r["diffusive"] > 0).sum())
     # normalised profiles
     for k in range(plan.n_segments):
         nv, nu = plan.shapes[k]
