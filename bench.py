@@ -128,7 +128,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=25.0,
+                    help="target of the CPU pilot-based sizing (the measured run usually takes about half)")
+    ap.add_argument("--launch", default="", help="blocks,threads,refill_min instead of autotuning")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -159,7 +161,11 @@ def main():
     plan = spx.Plan(cfgs, params, precision=32)
     setup_s = time.perf_counter() - t
     t = time.perf_counter()
-    launch = plan.launch if args.no_autotune else plan.autotune()
+    if args.launch:
+        b_, t_, r_ = (int(x) for x in args.launch.split(","))
+        launch = plan.set_launch(b_, t_, r_)
+    else:
+        launch = plan.launch if args.no_autotune else plan.autotune()
     tune_s = time.perf_counter() - t
     bufs = plan.allocate(profiles=True)
     wall, ms = time_steps(plan, bufs, args.seed, args.steps, args.warmup)

@@ -94,19 +94,23 @@ def test_backward_matches_autograd_reference():
 def test_backward_finite_differences():
     # central differences of the GPU forward itself, in float64 inputs rounded to FP32
     f, a, b, P, M, rho, fref = _inputs(B=4, J=12, K=3)
+    b = 40.0 * a                  # rate offsets comparable to a P, so every input matters
     gc = np.random.default_rng(5).normal(size=(4, 12, 3))
     g = spx.comp_backward(*_cuda(f, a, b, P, M, rho, fref, gc))
     L = lambda **kw: float((spx.comp_forward(*_cuda(*[kw.get(n, v) for n, v in zip(
         ("f", "a", "b", "P", "M", "rho", "fref"), (f, a, b, P, M, rho, fref))])).double().cpu().numpy() * gc).sum())
-    for name, base in zip(("a", "b", "M", "rho", "fref"), (a, b, M, rho, fref)):
-        for i in range(len(base)):
-            h = 1e-2 * abs(base[i]) + 1e-3
-            xp, xm = base.copy(), base.copy()
+    # FP32 forward: c carries ~1e-5 at.% rounding, so steps are a few % of each input
+    for name, base in zip(("a", "b", "M", "rho", "fref", "P", "f"), (a, b, M, rho, fref, P, f)):
+        flat = base.reshape(-1)
+        for i in range(0, flat.size, max(1, flat.size // 6)):
+            h = 2e-2 * abs(flat[i])
+            xp, xm = flat.copy(), flat.copy()
             xp[i] += h
             xm[i] -= h
-            fd = (L(**{name: xp}) - L(**{name: xm})) / (2 * h)
-            an = float(g[name][i])
-            assert abs(fd - an) <= 2e-2 * max(abs(fd), 1e-2), (name, i, fd, an)
+            fd = (L(**{name: xp.reshape(base.shape)}) - L(**{name: xm.reshape(base.shape)})) / (2 * h)
+            an = float(g[name].reshape(-1)[i])
+            noise = 4e-5 * np.abs(gc).sum() / (2 * h)
+            assert abs(fd - an) <= 2e-3 * abs(fd) + noise + 1e-4 * abs(fd) / 2e-2, (name, i, fd, an)
 
 
 def test_sqdist_kernel():
@@ -168,6 +172,6 @@ def test_power_rate_fit_from_compositions():
         opt.step()
     aa = (float(a_star[0]) * torch.exp(la - la[0])).detach().cpu().numpy()
     bb = torch.exp(lb).detach().cpu().numpy()
-    say(f"  fit: a={aa}, b={bb}, loss={float(loss):.3e}")
+    say(f"  fit: a={aa}, b={bb}, loss={float(loss.detach()):.3e}")
     assert np.allclose(aa, a_star, rtol=2e-2)
     assert np.allclose(bb, b_star, rtol=3e-2)
