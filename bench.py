@@ -130,7 +130,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=25.0,
                     help="target of the CPU pilot-based sizing (the measured run usually takes about half)")
-    ap.add_argument("--launch", default="", help="blocks,threads,refill_min instead of autotuning")
+    ap.add_argument("--launch", default="", help="blocks,threads,refill_min,ballistic_min instead of autotuning")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -162,8 +162,8 @@ def main():
     setup_s = time.perf_counter() - t
     t = time.perf_counter()
     if args.launch:
-        b_, t_, r_ = (int(x) for x in args.launch.split(","))
-        launch = plan.set_launch(b_, t_, r_)
+        b_, t_, r_, m_ = (int(x) for x in args.launch.split(","))
+        launch = plan.set_launch(b_, t_, r_, m_)
     else:
         launch = plan.launch if args.no_autotune else plan.autotune()
     tune_s = time.perf_counter() - t

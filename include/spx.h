@@ -160,14 +160,19 @@ int spx_plan_layout(const spx_plan* plan, uint64_t* h_bin_off, uint64_t* h_first
 int spx_run(spx_plan* plan, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters,
             double* d_profiles, spx_record* d_records, void* stream);
 
-/* Choose launch parameters of the FP32 transport (block size, waves per CU, refill
- * threshold) by timing short runs on `stream`; synchronous; tallies are unaffected. */
+/* Choose launch parameters of the FP32 transport (block size, refill and ballistic
+ * thresholds) by timing short runs on `stream`; synchronous; results are unaffected. */
 int spx_autotune(spx_plan* plan, void* stream);
 
-/* Current FP32-transport launch parameters: blocks, threads per block, refill threshold. */
-int spx_get_launch(const spx_plan* plan, int32_t* blocks, int32_t* threads, int32_t* refill_min);
-/* Override them (blocks <= 0: fill the device at the occupancy limit). */
-int spx_set_launch(spx_plan* plan, int32_t blocks, int32_t threads, int32_t refill_min);
+/* Current FP32-transport launch parameters: blocks, threads per block, refill threshold
+ * (a wave refills its dead lanes once at least this many are dead) and ballistic threshold
+ * (a wave runs ballistic flights once at least this many lanes are ballistic, else
+ * diffusive steps).  Any pointer may be NULL. */
+int spx_get_launch(const spx_plan* plan, int32_t* blocks, int32_t* threads, int32_t* refill_min,
+                   int32_t* ballistic_min);
+/* Override them: threads a multiple of 64 in [64, 1024], thresholds in [1, 64]; blocks <= 0
+ * (or above the resident limit) fills the device at the occupancy limit. */
+int spx_set_launch(spx_plan* plan, int32_t blocks, int32_t threads, int32_t refill_min, int32_t ballistic_min);
 
 /* Copy the FP64 scattering table to the host: h_theta[ne * ns] (row i = log10 eps node),
  * h_betamax[ne]. */

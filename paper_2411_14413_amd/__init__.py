@@ -158,12 +158,14 @@ class Plan:
 
     @property
     def launch(self):
-        b, t, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        check(lib().spx_get_launch(self._h, ctypes.byref(b), ctypes.byref(t), ctypes.byref(r)), "spx_get_launch")
-        return dict(blocks=b.value, threads=t.value, refill_min=r.value)
+        b, t, r, m = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().spx_get_launch(self._h, ctypes.byref(b), ctypes.byref(t), ctypes.byref(r), ctypes.byref(m)),
+              "spx_get_launch")
+        return dict(blocks=b.value, threads=t.value, refill_min=r.value, ballistic_min=m.value)
 
-    def set_launch(self, blocks: int = 0, threads: int = 256, refill_min: int = 1):
-        check(lib().spx_set_launch(self._h, int(blocks), int(threads), int(refill_min)), "spx_set_launch")
+    def set_launch(self, blocks: int = 0, threads: int = 256, refill_min: int = 8, ballistic_min: int = 8):
+        check(lib().spx_set_launch(self._h, int(blocks), int(threads), int(refill_min), int(ballistic_min)),
+              "spx_set_launch")
         return self.launch
 
     # -- introspection ---------------------------------------------------------------------

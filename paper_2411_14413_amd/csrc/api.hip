@@ -218,6 +218,12 @@ template <typename R> static SegDev<R> to_device(const Plan* P, const SegHost& s
         d.sub_v[i] = (R)s.sub_v[i];
     }
     d.cat_R2 = (R)(s.cat_R * s.cat_R);
+    d.cat_nc = (R)dot(s.cat_n, s.cat_c);
+    d.cat_uc = (R)dot(s.cat_u, s.cat_c);
+    d.cat_vc = (R)dot(s.cat_v, s.cat_c);
+    d.sub_nc = (R)dot(s.sub_n, s.sub_c);
+    d.sub_uc = (R)dot(s.sub_u, s.sub_c);
+    d.sub_vc = (R)dot(s.sub_v, s.sub_c);
     d.half_u = (R)s.half_u;
     d.half_v = (R)s.half_v;
     d.inv_du = (R)(1.0 / s.du);
@@ -381,7 +387,7 @@ static int create(const spx_config* cfgs, int n_cfgs, const spx_params* prm, Pla
         return SPX_EDEVICE;
     }
     int bpc = 0;
-    if (occupancy_transport32(P->threads, &bpc) != SPX_OK || bpc < 1) {
+    if (occupancy_transport32(P, P->threads, &bpc) != SPX_OK || bpc < 1) {
         release(P);
         set_error("occupancy query failed for the transport kernel");
         return SPX_EDEVICE;
@@ -406,6 +412,7 @@ static int run(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters,
     key.blocks = P->blocks;
     key.threads = P->threads;
     key.refill = P->refill_min;
+    key.bmin = P->ballistic_min;
     if (!P->graph_exec || !(key == P->graph_key)) {
         if (P->graph_exec) {
             SPX_HIP(hipGraphExecDestroy(P->graph_exec));
@@ -417,7 +424,8 @@ static int run(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters,
         }
         SPX_HIP(hipStreamBeginCapture(P->work_stream, hipStreamCaptureModeThreadLocal));
         const int rc = launch_transport32(P, seed, d_counts, d_counters, d_profiles, d_records, P->work_stream,
-                                          P->d_tfirst, P->n_tickets, P->blocks, P->threads, P->refill_min);
+                                          P->d_tfirst, P->n_tickets, P->blocks, P->threads, P->refill_min,
+                                          P->ballistic_min);
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(P->work_stream, &g);
         if (rc != SPX_OK) {
@@ -454,20 +462,20 @@ static int autotune(Plan* P, hipStream_t st)
     if (rc == SPX_OK && hipMemcpyAsync(d_tf, tf.data(), sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess)
         rc = SPX_EDEVICE;
     float best = 1e30f;
-    int bb = P->blocks, bt = P->threads, br = P->refill_min;
+    int bb = P->blocks, bt = P->threads, br = P->refill_min, bm = P->ballistic_min;
     const int thread_opts[] = {256, 512, 1024};
-    const int refill_opts[] = {1, 8, 24};
+    const int mode_opts[][2] = {{1, 1}, {8, 8}, {16, 16}, {16, 32}, {32, 32}};
     for (int t : thread_opts) {
         if (rc != SPX_OK) break;
         int bpc = 0;
-        if (occupancy_transport32(t, &bpc) != SPX_OK || bpc < 1) continue;
-        for (int r : refill_opts) {
+        if (occupancy_transport32(P, t, &bpc) != SPX_OK || bpc < 1) continue;
+        for (const auto& ro : mode_opts) {
             const int blocks = bpc * P->n_cu;
             float ms_min = 1e30f;
             for (int rep = 0; rep < 2 && rc == SPX_OK; ++rep) {
                 if (hipEventRecord(e0, st) != hipSuccess) rc = SPX_EDEVICE;
                 if (rc == SPX_OK) rc = launch_transport32(P, 0x5eed, d_counts, d_ctr, nullptr, nullptr, st, d_tf, tf[n],
-                                                          blocks, t, r);
+                                                          blocks, t, ro[0], ro[1]);
                 if (rc == SPX_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
                     rc = SPX_EDEVICE;
                 float ms = 0.f;
@@ -477,7 +485,8 @@ static int autotune(Plan* P, hipStream_t st)
                 best = ms_min;
                 bb = blocks;
                 bt = t;
-                br = r;
+                br = ro[0];
+                bm = ro[1];
             }
         }
     }
@@ -493,6 +502,7 @@ static int autotune(Plan* P, hipStream_t st)
     P->blocks = bb;
     P->threads = bt;
     P->refill_min = br;
+    P->ballistic_min = bm;
     return SPX_OK;
 }
 
@@ -567,28 +577,32 @@ int spx_autotune(spx_plan* P, void* stream)
     return autotune(P, (hipStream_t)stream);
 }
 
-int spx_get_launch(const spx_plan* P, int32_t* blocks, int32_t* threads, int32_t* refill_min)
+int spx_get_launch(const spx_plan* P, int32_t* blocks, int32_t* threads, int32_t* refill_min,
+                   int32_t* ballistic_min)
 {
     if (!P) return fail("null plan");
     if (blocks) *blocks = P->blocks;
     if (threads) *threads = P->threads;
     if (refill_min) *refill_min = P->refill_min;
+    if (ballistic_min) *ballistic_min = P->ballistic_min;
     return SPX_OK;
 }
 
-int spx_set_launch(spx_plan* P, int32_t blocks, int32_t threads, int32_t refill_min)
+int spx_set_launch(spx_plan* P, int32_t blocks, int32_t threads, int32_t refill_min, int32_t ballistic_min)
 {
     if (!P) return fail("null plan");
     if (threads < 64 || threads > 1024 || (threads & 63)) return fail("threads must be a multiple of 64 in [64, 1024]");
     if (refill_min < 1 || refill_min > 64) return fail("refill_min must be in [1, 64]");
+    if (ballistic_min < 1 || ballistic_min > 64) return fail("ballistic_min must be in [1, 64]");
     int bpc = 0;
-    SPX_TRY(occupancy_transport32(threads, &bpc));
+    SPX_TRY(occupancy_transport32(P, threads, &bpc));
     if (bpc < 1) return fail("transport kernel does not fit with this block size");
     // a persistent grid larger than the resident limit would still be correct, but it is never useful
     const int limit = bpc * P->n_cu;
     P->blocks = (blocks <= 0 || blocks > limit) ? limit : blocks;
     P->threads = threads;
     P->refill_min = refill_min;
+    P->ballistic_min = ballistic_min;
     return SPX_OK;
 }
 

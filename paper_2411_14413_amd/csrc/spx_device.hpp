@@ -52,14 +52,21 @@ template <> __device__ __forceinline__ double u01<double>(uint32_t x)
 // --------------------------------------------------------------------------
 // Math overloads for R.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+// FP32 uses the native VALU transcendentals (v_sqrt, v_log: log2, v_exp: exp2, v_sin and
+// v_cos taking revolutions, v_rcp), each within a few ulp on the ranges used here; FP64 uses
+// the correctly rounded library functions.
+__device__ __forceinline__ float m_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float m_log(float x) { return logf(x); }
-__device__ __forceinline__ double m_log(double x) { return log(x); }
-__device__ __forceinline__ float m_log2(float x) { return log2f(x); }
+__device__ __forceinline__ float m_log2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ double m_log2(double x) { return log2(x); }
-__device__ __forceinline__ float m_exp(float x) { return expf(x); }
+__device__ __forceinline__ float m_log(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994530942f; }
+__device__ __forceinline__ double m_log(double x) { return log(x); }
+__device__ __forceinline__ float m_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.44269504088896340736f); }
 __device__ __forceinline__ double m_exp(double x) { return exp(x); }
+__device__ __forceinline__ float m_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double m_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float m_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double m_div(double a, double b) { return a / b; }
 __device__ __forceinline__ float m_erf(float x) { return erff(x); }
 __device__ __forceinline__ double m_erf(double x) { return erf(x); }
 __device__ __forceinline__ float m_ninv(float p) { return normcdfinvf(p); }
@@ -69,9 +76,19 @@ __device__ __forceinline__ double m_floor(double x) { return floor(x); }
 __device__ __forceinline__ bool m_finite(float x) { return isfinite(x); }
 __device__ __forceinline__ bool m_finite(double x) { return isfinite(x); }
 // sin and cos of 2 pi u for u in ]0, 1]
-__device__ __forceinline__ void m_sincos2pi(float u, float* s, float* c) { sincospif(2.0f * u, s, c); }
+__device__ __forceinline__ void m_sincos2pi(float u, float* s, float* c)
+{
+    *s = __builtin_amdgcn_sinf(u);
+    *c = __builtin_amdgcn_cosf(u);
+}
 __device__ __forceinline__ void m_sincos2pi(double u, double* s, double* c) { sincospi(2.0 * u, s, c); }
-__device__ __forceinline__ void m_sincos(float x, float* s, float* c) { sincosf(x, s, c); }
+// sin and cos of an angle in [0, pi] (radians)
+__device__ __forceinline__ void m_sincos(float x, float* s, float* c)
+{
+    const float r = x * 0.15915494309189533577f;
+    *s = __builtin_amdgcn_sinf(r);
+    *c = __builtin_amdgcn_cosf(r);
+}
 __device__ __forceinline__ void m_sincos(double x, double* s, double* c) { sincos(x, s, c); }
 template <typename R> __device__ __forceinline__ R m_inf();
 template <> __device__ __forceinline__ float m_inf<float>() { return __builtin_huge_valf(); }
@@ -84,7 +101,9 @@ template <> __device__ __forceinline__ double m_inf<double>() { return __builtin
 template <typename R> struct SegDev {
     R cat_c[3], cat_n[3], cat_u[3], cat_v[3];
     R cat_R2;
+    R cat_nc, cat_uc, cat_vc;             // n.c, u.c, v.c of the target
     R sub_c[3], sub_n[3], sub_u[3], sub_v[3];
+    R sub_nc, sub_uc, sub_vc;             // n.c, u.c, v.c of the substrate
     R half_u, half_v, inv_du, inv_dv, sub_R2;
     R ch_R2, zlo, zhi;
     R rt_mu, rt_sig, PhiA, QB, dPhi;      // racetrack truncated normal
@@ -176,7 +195,7 @@ __device__ __forceinline__ void launch(const SegDev<R>& s, uint4 r0, uint4 r1, R
     for (int i = 0; i < 3; ++i) x[i] = s.cat_c[i] + rr * (cp * s.cat_u[i] + sp * s.cat_v[i]);
     // Thompson energy: [E/(E+U_s)]^2 proportional to RN up to the cut-off
     const R se = m_sqrt(u2) * s.smax;
-    E = s.Us * se / ((R)1 - se);
+    E = m_div(s.Us * se, (R)1 - se);
     // cosine emission: cos(theta) = sqrt(RN)
     const R mu = m_sqrt(u3), st = m_sqrt((R)1 - u3);
     R sf, cf;
@@ -191,12 +210,12 @@ __device__ __forceinline__ R lambda_m(const SegDev<R>& s, const TabDev<R>& tb, R
 {
     const R bm = tab_betamax(tb, m_log2(E) * tb.xs + s.xo_stat);
     const R nsig = s.n_pia2 * bm * bm;
-    if (!s.gas_motion) return (R)1 / nsig;
+    if (!s.gas_motion) return m_rcp(nsig);
     // moving gas: the collision rate uses the Maxwellian mean relative speed <g>(v)
     const R v = m_sqrt(E * s.two_over_Ms);
     const R xx = v * s.inv_vg;
-    const R g = s.vg * ((xx + (R)0.5 / xx) * m_erf(xx) + m_exp(-xx * xx) * (R)0.56418958354775628695);
-    return v / (nsig * g);
+    const R g = s.vg * ((xx + m_div((R)0.5, xx)) * m_erf(xx) + m_exp(-xx * xx) * (R)0.56418958354775628695);
+    return m_div(v, nsig * g);
 }
 
 struct Hit {
@@ -205,6 +224,7 @@ struct Hit {
 };
 
 // Nearest surface with 0 < t <= ell; exact ties keep substrate, then cathode, then chamber.
+// Planes use the precomputed n.c, u.c, v.c: t = (n.c - n.x)/(n.d), q.u = u.x + t u.d - u.c.
 template <typename R>
 __device__ __forceinline__ Hit hit_test(const SegDev<R>& s, const R* x, const R* d, R ell, R& t_hit, bool first)
 {
@@ -213,11 +233,10 @@ __device__ __forceinline__ Hit hit_test(const SegDev<R>& s, const R* x, const R*
     {   // substrate plate
         const R dn = dot3(d, s.sub_n);
         if (dn != (R)0) {
-            const R w[3] = {s.sub_c[0] - x[0], s.sub_c[1] - x[1], s.sub_c[2] - x[2]};
-            const R t = dot3(w, s.sub_n) / dn;
+            const R t = (s.sub_nc - dot3(x, s.sub_n)) * m_rcp(dn);
             if (t > (R)0) {
-                const R q[3] = {t * d[0] - w[0], t * d[1] - w[1], t * d[2] - w[2]};
-                const R qu = dot3(q, s.sub_u), qv = dot3(q, s.sub_v);
+                const R qu = dot3(x, s.sub_u) + t * dot3(d, s.sub_u) - s.sub_uc;
+                const R qv = dot3(x, s.sub_v) + t * dot3(d, s.sub_v) - s.sub_vc;
                 const bool inside = (s.shape == 0) ? (fabs(qu) <= s.half_u && fabs(qv) <= s.half_v)
                                                    : (qu * qu + qv * qv <= s.sub_R2);
                 if (inside) {
@@ -241,11 +260,10 @@ __device__ __forceinline__ Hit hit_test(const SegDev<R>& s, const R* x, const R*
     if (!first) {
         const R dn = dot3(d, s.cat_n);
         if (dn != (R)0) {
-            const R w[3] = {s.cat_c[0] - x[0], s.cat_c[1] - x[1], s.cat_c[2] - x[2]};
-            const R t = dot3(w, s.cat_n) / dn;
+            const R t = (s.cat_nc - dot3(x, s.cat_n)) * m_rcp(dn);
             if (t > (R)0 && t < best) {
-                const R q[3] = {t * d[0] - w[0], t * d[1] - w[1], t * d[2] - w[2]};
-                const R qu = dot3(q, s.cat_u), qv = dot3(q, s.cat_v);
+                const R qu = dot3(x, s.cat_u) + t * dot3(d, s.cat_u) - s.cat_uc;
+                const R qv = dot3(x, s.cat_v) + t * dot3(d, s.cat_v) - s.cat_vc;
                 if (qu * qu + qv * qv <= s.cat_R2) {
                     best = t;
                     state = HIT_WALL;
@@ -263,15 +281,11 @@ __device__ __forceinline__ Hit hit_test(const SegDev<R>& s, const R* x, const R*
             R disc = b * b - a * c;
             disc = disc > (R)0 ? disc : (R)0;
             const R sq = m_sqrt(disc);
-            R t = (b <= (R)0) ? (-b + sq) / a : -c / (b + sq);
+            R t = (b <= (R)0) ? (sq - b) * m_rcp(a) : -c * m_rcp(b + sq);
             tc = t > (R)0 ? t : (R)0;
         }
-        if (d[2] > (R)0) {
-            R t = (s.zhi - x[2]) / d[2];
-            t = t > (R)0 ? t : (R)0;
-            tc = t < tc ? t : tc;
-        } else if (d[2] < (R)0) {
-            R t = (s.zlo - x[2]) / d[2];
+        if (d[2] != (R)0) {
+            R t = ((d[2] > (R)0 ? s.zhi : s.zlo) - x[2]) * m_rcp(d[2]);
             t = t > (R)0 ? t : (R)0;
             tc = t < tc ? t : tc;
         }
@@ -318,12 +332,12 @@ __device__ __forceinline__ void collide(const SegDev<R>& s, const TabDev<R>& tb,
     R st, ct, sp, cp;
     m_sincos(th, &st, &ct);
     m_sincos2pi(u_phi, &sp, &cp);
-    const R inv = (R)1 / gm;
+    const R inv = m_rcp(gm);
     const R gu = g[0] * inv, gv = g[1] * inv, gw = g[2] * inv;
     R n0, n1, n2;
     if (fabs(gw) < (R)0.99999) {
         const R rho = m_sqrt(((R)1 - gw) * ((R)1 + gw));
-        const R ir = (R)1 / rho;
+        const R ir = m_rcp(rho);
         n0 = gu * ct + st * (gu * gw * cp - gv * sp) * ir;
         n1 = gv * ct + st * (gv * gw * cp + gu * sp) * ir;
         n2 = gw * ct - rho * st * cp;
@@ -338,7 +352,7 @@ __device__ __forceinline__ void collide(const SegDev<R>& s, const TabDev<R>& tb,
     const R vp2 = dot3(vp, vp);
     E = s.half_Ms * vp2;
     if (vp2 > (R)0) {
-        const R iv = (R)1 / m_sqrt(vp2);
+        const R iv = m_rcp(m_sqrt(vp2));
         d[0] = vp[0] * iv;
         d[1] = vp[1] * iv;
         d[2] = vp[2] * iv;
@@ -384,18 +398,18 @@ struct Term {
     int bin;
 };
 
-// One flight of a live particle: event number p.e + 1.  Returns the terminal
-// outcome (HIT_NONE if the particle is still in the gas afterwards).
-template <typename R>
-__device__ __forceinline__ Term step(const SegDev<R>& s, const TabDev<R>& tb, uint32_t k0, uint32_t k1, uint32_t pid,
-                                     uint32_t cap, Particle<R>& p)
+// One flight of a live particle in state MODE (ST_BALLISTIC or ST_DIFFUSIVE): event
+// number p.e + 1.  Returns the terminal outcome (HIT_NONE if still in the gas).
+template <typename R, int MODE>
+__device__ __forceinline__ Term step_mode(const SegDev<R>& s, const TabDev<R>& tb, uint32_t k0, uint32_t k1,
+                                          uint32_t pid, uint32_t cap, Particle<R>& p)
 {
     if (p.e >= cap) return Term{HIT_ESCAPED, -1};
     const uint32_t e = p.e + 1;
     p.e = e;
     const uint4 r = philox4x32_10(make_uint4(pid, e, s.cfgcat, 0u), k0, k1);
     R ell;
-    if (p.st == ST_BALLISTIC) {
+    if (MODE == ST_BALLISTIC) {
         ell = s.vacuum ? m_inf<R>() : -lambda_m(s, tb, p.E) * m_log(u01<R>(r.x));
     } else {
         ell = s.vacuum ? m_inf<R>() : diffusive_draw(s, r, p.d);
@@ -410,7 +424,7 @@ __device__ __forceinline__ Term step(const SegDev<R>& s, const TabDev<R>& tb, ui
     if (!(ell < m_inf<R>())) return Term{HIT_ESCAPED, -1};
 #pragma unroll
     for (int i = 0; i < 3; ++i) kahan_add(p.x[i], p.xc[i], ell * p.d[i]);
-    if (p.st == ST_BALLISTIC) {
+    if (MODE == ST_BALLISTIC) {
         R V[3] = {(R)0, (R)0, (R)0};
         if (s.gas_motion) gas_velocity(s, philox4x32_10(make_uint4(pid, e, s.cfgcat, 1u), k0, k1), V);
         collide(s, tb, p.E, p.d, V, u01<R>(r.y), u01<R>(r.z));
@@ -421,6 +435,14 @@ __device__ __forceinline__ Term step(const SegDev<R>& s, const TabDev<R>& tb, ui
     }
     if (!(m_finite(p.x[0]) && m_finite(p.x[1]) && m_finite(p.x[2]) && m_finite(p.E))) return Term{HIT_ESCAPED, -1};
     return Term{HIT_NONE, -1};
+}
+
+template <typename R>
+__device__ __forceinline__ Term step(const SegDev<R>& s, const TabDev<R>& tb, uint32_t k0, uint32_t k1, uint32_t pid,
+                                     uint32_t cap, Particle<R>& p)
+{
+    return p.st == ST_BALLISTIC ? step_mode<R, ST_BALLISTIC>(s, tb, k0, k1, pid, cap, p)
+                                : step_mode<R, ST_DIFFUSIVE>(s, tb, k0, k1, pid, cap, p);
 }
 
 template <typename R>

@@ -61,8 +61,15 @@ struct TransportArgs {
     uint32_t k0, k1;            // Philox key (seed words)
     uint32_t cap;
     int32_t n_seg;
-    int32_t refill_min;
+    int32_t refill_min;         // refill a wave's dead lanes once at least this many
+    int32_t ballistic_min;      // run ballistic flights once at least this many lanes are ballistic
+    uint32_t n_bins;            // tally bins of the plan
+    int32_t lds_counters;       // per-segment counters privatised in LDS
+    int32_t lds_tally;          // whole tally privatised in LDS (u32 per bin)
 };
+
+constexpr size_t LDS_COUNTERS_MAX = 16384;   // bytes: up to 292 segments
+constexpr size_t LDS_TALLY_MAX = 49152;      // bytes: up to 12288 bins
 
 struct GraphKey {
     uint64_t seed = 0;
@@ -70,11 +77,12 @@ struct GraphKey {
     void* counters = nullptr;
     void* profiles = nullptr;
     void* records = nullptr;
-    int blocks = 0, threads = 0, refill = 0;
+    int blocks = 0, threads = 0, refill = 0, bmin = 0;
     bool operator==(const GraphKey& o) const
     {
         return seed == o.seed && counts == o.counts && counters == o.counters && profiles == o.profiles &&
-               records == o.records && blocks == o.blocks && threads == o.threads && refill == o.refill;
+               records == o.records && blocks == o.blocks && threads == o.threads && refill == o.refill &&
+               bmin == o.bmin;
     }
 };
 
@@ -104,7 +112,7 @@ struct spx_plan {
     double* d_seg_norm = nullptr;           // [n_seg]
     uint64_t n_tickets = 0;
 
-    int blocks = 0, threads = 256, refill_min = 1;
+    int blocks = 0, threads = 256, refill_min = 8, ballistic_min = 8;
     int max_blocks_per_cu = 0, n_cu = 0;
 
     hipGraph_t graph = nullptr;
@@ -117,8 +125,8 @@ using Plan = spx_plan;
 int build_tables(Plan* P);
 int launch_transport32(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
                        spx_record* d_records, hipStream_t st, const uint64_t* tfirst, uint64_t total,
-                       int blocks, int threads, int refill_min);
+                       int blocks, int threads, int refill_min, int ballistic_min);
 int launch_transport64(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
                        spx_record* d_records, hipStream_t st);
-int occupancy_transport32(int threads, int* blocks_per_cu);
+int occupancy_transport32(const Plan* P, int threads, int* blocks_per_cu);
 }  // namespace spx

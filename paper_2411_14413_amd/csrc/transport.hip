@@ -42,8 +42,29 @@ __device__ __forceinline__ void write_record(spx_record* rec, const SegDev<R>& s
     rec[s.first_rec + pid] = r;
 }
 
-__global__ void __launch_bounds__(1024) k_transport32(TransportArgs a)
+// One flight of the lanes of this wave that are in state MODE.  When every such lane is
+// in the same segment the segment constants come through scalar loads.
+template <int MODE>
+__device__ __forceinline__ Term wave_step(const TransportArgs& a, const SegDev<float>* __restrict__ segs, int seg,
+                                          uint32_t pid, Particle<float>& p)
 {
+    const int s0 = __builtin_amdgcn_readfirstlane(seg);
+    if (__ballot(seg != s0) == 0) return step_mode<float, MODE>(segs[s0], a.tab, a.k0, a.k1, pid, a.cap, p);
+    return step_mode<float, MODE>(segs[seg], a.tab, a.k0, a.k1, pid, a.cap, p);
+}
+
+// Dynamic LDS: per-segment counters (u64, when lds_counters) then the tally (u32, when lds_tally).
+__global__ void __launch_bounds__(1024) k_transport32(TransportArgs a, const SegDev<float>* __restrict__ segs)
+{
+    extern __shared__ unsigned long long lds[];
+    unsigned long long* lcnt = lds;
+    uint32_t* ltally = (uint32_t*)(lds + (a.lds_counters ? (size_t)a.n_seg * N_COUNTERS : 0));
+    if (a.lds_counters)
+        for (int i = threadIdx.x; i < a.n_seg * N_COUNTERS; i += blockDim.x) lcnt[i] = 0;
+    if (a.lds_tally)
+        for (uint32_t i = threadIdx.x; i < a.n_bins; i += blockDim.x) ltally[i] = 0;
+    __syncthreads();
+
     const int lane = threadIdx.x & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     Particle<float> p;
@@ -54,6 +75,17 @@ __global__ void __launch_bounds__(1024) k_transport32(TransportArgs a)
     int acc_seg = -1;
     uint32_t acc[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0};
     bool drained = false;   // wave-uniform: the ticket space is exhausted
+
+    auto flush_acc = [&]() {
+        if (acc_seg < 0) return;
+        if (a.lds_counters) {
+#pragma unroll
+            for (int i = 0; i < N_COUNTERS; ++i)
+                if (acc[i]) atomicAdd(&lcnt[acc_seg * N_COUNTERS + i], (unsigned long long)acc[i]);
+        } else {
+            add_counters(a.counters + (size_t)acc_seg * N_COUNTERS, acc);
+        }
+    };
 
     for (;;) {
         const uint64_t dead = __ballot(p.st == ST_DEAD);
@@ -75,36 +107,54 @@ __global__ void __launch_bounds__(1024) k_transport32(TransportArgs a)
                     const int sg = (int)a.torder[lo];
                     pid = (uint32_t)(my - a.tfirst[lo]);
                     if (sg != acc_seg) {
-                        if (acc_seg >= 0) add_counters(a.counters + (size_t)acc_seg * N_COUNTERS, acc);
+                        flush_acc();
 #pragma unroll
                         for (int i = 0; i < N_COUNTERS; ++i) acc[i] = 0;
                         acc_seg = sg;
                     }
                     seg = sg;
-                    start(a.segs[seg], a.k0, a.k1, pid, p);
+                    start(segs[seg], a.k0, a.k1, pid, p);
                     acc[C_LAUNCHED] += 1;
                 }
             }
         }
-        if (__ballot(p.st != ST_DEAD) == 0) {
+        const uint64_t B = __ballot(p.st == ST_BALLISTIC);
+        const uint64_t D = __ballot(p.st == ST_DIFFUSIVE);
+        if ((B | D) == 0) {
             if (drained) break;
             continue;
         }
-        if (p.st != ST_DEAD) {
-            const SegDev<float>& s = a.segs[seg];
-            const Term t = step(s, a.tab, a.k0, a.k1, pid, a.cap, p);
+        // Run one kind of event per iteration: ballistic flights only once enough lanes are
+        // ballistic (or nothing else is left), so rare ballistic lanes do not drag the long
+        // collision path into most iterations of a thermalised wave.
+        const int mode = (B != 0 && (__popcll(B) >= a.ballistic_min || D == 0)) ? ST_BALLISTIC : ST_DIFFUSIVE;
+        if (p.st == mode) {
+            const Term t = (mode == ST_BALLISTIC) ? wave_step<ST_BALLISTIC>(a, segs, seg, pid, p)
+                                                  : wave_step<ST_DIFFUSIVE>(a, segs, seg, pid, p);
             if (t.state != HIT_NONE) {
+                const SegDev<float>& s = segs[seg];
                 acc[t.state == HIT_DEPOSITED ? C_DEPOSITED : (t.state == HIT_WALL ? C_WALL : C_ESCAPED)] += 1;
                 acc[C_COLLISIONS] += p.ncoll;
                 acc[C_DIFFUSIVE] += p.ndiff;
                 acc[C_THERMALIZED] += (p.st == ST_DIFFUSIVE) ? 1u : 0u;
-                if (t.state == HIT_DEPOSITED) atomicAdd(&a.counts[s.bin_off + (uint64_t)t.bin], 1ull);
+                if (t.state == HIT_DEPOSITED) {
+                    const uint64_t b = s.bin_off + (uint64_t)t.bin;
+                    if (a.lds_tally) atomicAdd(&ltally[b], 1u);
+                    else atomicAdd(&a.counts[b], 1ull);
+                }
                 if (a.records) write_record(a.records, s, pid, p, t);
                 p.st = ST_DEAD;
             }
         }
     }
-    if (acc_seg >= 0) add_counters(a.counters + (size_t)acc_seg * N_COUNTERS, acc);
+    flush_acc();
+    __syncthreads();
+    if (a.lds_counters)
+        for (int i = threadIdx.x; i < a.n_seg * N_COUNTERS; i += blockDim.x)
+            if (lcnt[i]) atomicAdd(&a.counters[i], lcnt[i]);
+    if (a.lds_tally)
+        for (uint32_t i = threadIdx.x; i < a.n_bins; i += blockDim.x)
+            if (ltally[i]) atomicAdd(&a.counts[i], (unsigned long long)ltally[i]);
 }
 
 __global__ void __launch_bounds__(256) k_transport64(const SegDev<double>* __restrict__ segp, TabDev<double> tab,
@@ -188,15 +238,27 @@ static int launch_normalize(Plan* P, const uint64_t* d_counts, double* d_profile
     return SPX_OK;
 }
 
-int occupancy_transport32(int threads, int* blocks_per_cu)
+// Dynamic LDS of the FP32 transport for a plan: counters if they fit, tally if it fits.
+size_t transport32_lds(const Plan* P, bool* lds_counters, bool* lds_tally)
 {
-    SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_transport32, threads, 0));
+    const size_t cbytes = (size_t)P->n_seg * N_COUNTERS * sizeof(unsigned long long);
+    const size_t tbytes = (size_t)P->n_bins_total * sizeof(uint32_t);
+    *lds_counters = cbytes <= LDS_COUNTERS_MAX;
+    *lds_tally = tbytes <= LDS_TALLY_MAX;
+    return (*lds_counters ? cbytes : 0) + (*lds_tally ? tbytes : 0);
+}
+
+int occupancy_transport32(const Plan* P, int threads, int* blocks_per_cu)
+{
+    bool lc, lt;
+    const size_t smem = transport32_lds(P, &lc, &lt);
+    SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_transport32, threads, smem));
     return SPX_OK;
 }
 
 int launch_transport32(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
                        spx_record* d_records, hipStream_t st, const uint64_t* tfirst, uint64_t total, int blocks,
-                       int threads, int refill_min)
+                       int threads, int refill_min, int ballistic_min)
 {
     SPX_TRY(launch_zero_and_tail(P, d_counts, d_counters, P->d_ticket, st));
     TransportArgs a;
@@ -218,7 +280,14 @@ int launch_transport32(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_c
     a.cap = P->params.event_cap;
     a.n_seg = P->n_seg;
     a.refill_min = refill_min;
-    hipLaunchKernelGGL(k_transport32, dim3(blocks), dim3(threads), 0, st, a);
+    a.ballistic_min = ballistic_min;
+    a.n_bins = (uint32_t)P->n_bins_total;
+    bool lc, lt;
+    const size_t smem = transport32_lds(P, &lc, &lt);
+    a.lds_counters = lc ? 1 : 0;
+    a.lds_tally = lt ? 1 : 0;
+    hipLaunchKernelGGL(k_transport32, dim3(blocks), dim3(threads), smem, st, a,
+                       (const SegDev<float>*)P->d_seg32);
     SPX_HIP(hipGetLastError());
     if (d_profiles) SPX_TRY(launch_normalize(P, d_counts, d_profiles, st));
     return SPX_OK;
