@@ -24,13 +24,19 @@ enum : int { C_LAUNCHED = 0, C_DEPOSITED, C_WALL, C_ESCAPED, C_COLLISIONS, C_DIF
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11); the key words are uniform
 // across the launch, so their schedule lives in scalar registers.
 // --------------------------------------------------------------------------
+// Three-input XOR in one VALU instruction (gfx950 v_bitop3, truth table 0x96 = a ^ b ^ c).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
-        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1,
+        c = make_uint4(xor3((uint32_t)(p1 >> 32), c.y, k0), (uint32_t)p1, xor3((uint32_t)(p0 >> 32), c.w, k1),
                        (uint32_t)p0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -42,7 +48,8 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1
 template <typename R> __device__ __forceinline__ R u01(uint32_t x);
 template <> __device__ __forceinline__ float u01<float>(uint32_t x)
 {
-    return (float)((x >> 8) + 1u) * 0x1p-24f;
+    // (k + 1) 2^-24 with k < 2^24: exact, one fused multiply-add
+    return __builtin_fmaf((float)(x >> 8), 0x1p-24f, 0x1p-24f);
 }
 template <> __device__ __forceinline__ double u01<double>(uint32_t x)
 {
@@ -218,18 +225,18 @@ __device__ __forceinline__ R lambda_m(const SegDev<R>& s, const TabDev<R>& tb, R
     return m_div(v, nsig * g);
 }
 
-struct Hit {
+struct HitF {
     int state;     // HIT_NONE / HIT_DEPOSITED / HIT_WALL
-    int bin;
 };
 
 // Nearest surface with 0 < t <= ell; exact ties keep substrate, then cathode, then chamber.
 // Planes use the precomputed n.c, u.c, v.c: t = (n.c - n.x)/(n.d), q.u = u.x + t u.d - u.c.
 template <typename R>
-__device__ __forceinline__ Hit hit_test(const SegDev<R>& s, const R* x, const R* d, R ell, R& t_hit, bool first)
+__device__ __forceinline__ HitF hit_test(const SegDev<R>& s, const R* x, const R* d, R ell, R& t_hit, R& qu_hit,
+                                         R& qv_hit, bool first)
 {
     R best = m_inf<R>();
-    int state = HIT_NONE, bin = -1;
+    int state = HIT_NONE;
     {   // substrate plate
         const R dn = dot3(d, s.sub_n);
         if (dn != (R)0) {
@@ -241,16 +248,9 @@ __device__ __forceinline__ Hit hit_test(const SegDev<R>& s, const R* x, const R*
                                                    : (qu * qu + qv * qv <= s.sub_R2);
                 if (inside) {
                     best = t;
-                    if (dn < (R)0) {
-                        int iu = (int)m_floor((qu + s.half_u) * s.inv_du);
-                        int iv = (int)m_floor((qv + s.half_v) * s.inv_dv);
-                        iu = iu < 0 ? 0 : (iu > s.nu - 1 ? s.nu - 1 : iu);
-                        iv = iv < 0 ? 0 : (iv > s.nv - 1 ? s.nv - 1 : iv);
-                        state = HIT_DEPOSITED;
-                        bin = iv * s.nu + iu;
-                    } else {
-                        state = HIT_WALL;
-                    }
+                    qu_hit = qu;
+                    qv_hit = qv;
+                    state = (dn < (R)0) ? HIT_DEPOSITED : HIT_WALL;
                 }
             }
         }
@@ -267,7 +267,6 @@ __device__ __forceinline__ Hit hit_test(const SegDev<R>& s, const R* x, const R*
                 if (qu * qu + qv * qv <= s.cat_R2) {
                     best = t;
                     state = HIT_WALL;
-                    bin = -1;
                 }
             }
         }
@@ -292,15 +291,21 @@ __device__ __forceinline__ Hit hit_test(const SegDev<R>& s, const R* x, const R*
         if (tc < best) {
             best = tc;
             state = HIT_WALL;
-            bin = -1;
         }
     }
-    if (!(best <= ell)) {
-        state = HIT_NONE;
-        bin = -1;
-    }
+    if (!(best <= ell)) state = HIT_NONE;
     t_hit = best;
-    return Hit{state, bin};
+    return HitF{state};
+}
+
+// Tally bin of a deposit at in-plane coordinates (qu, qv) of the substrate (clamped).
+template <typename R> __device__ __forceinline__ int tally_bin(const SegDev<R>& s, R qu, R qv)
+{
+    int iu = (int)m_floor((qu + s.half_u) * s.inv_du);
+    int iv = (int)m_floor((qv + s.half_v) * s.inv_dv);
+    iu = iu < 0 ? 0 : (iu > s.nu - 1 ? s.nu - 1 : iu);
+    iv = iv < 0 ? 0 : (iv > s.nv - 1 ? s.nv - 1 : iv);
+    return iv * s.nu + iu;
 }
 
 // Maxwellian partner velocity from one Philox block (Box-Muller).
@@ -414,12 +419,12 @@ __device__ __forceinline__ Term step_mode(const SegDev<R>& s, const TabDev<R>& t
     } else {
         ell = s.vacuum ? m_inf<R>() : diffusive_draw(s, r, p.d);
     }
-    R t;
-    const Hit h = hit_test(s, p.x, p.d, ell, t, e == 1u);
+    R t, qu = (R)0, qv = (R)0;
+    const HitF h = hit_test(s, p.x, p.d, ell, t, qu, qv, e == 1u);
     if (h.state != HIT_NONE) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) kahan_add(p.x[i], p.xc[i], t * p.d[i]);
-        return Term{h.state, h.bin};
+        return Term{h.state, h.state == HIT_DEPOSITED ? tally_bin(s, qu, qv) : -1};
     }
     if (!(ell < m_inf<R>())) return Term{HIT_ESCAPED, -1};
 #pragma unroll
@@ -430,10 +435,12 @@ __device__ __forceinline__ Term step_mode(const SegDev<R>& s, const TabDev<R>& t
         collide(s, tb, p.E, p.d, V, u01<R>(r.y), u01<R>(r.z));
         ++p.ncoll;
         if (p.E <= s.E_th) p.st = ST_DIFFUSIVE;
+        if (!(m_finite(p.x[0]) && m_finite(p.x[1]) && m_finite(p.x[2]) && m_finite(p.E)))
+            return Term{HIT_ESCAPED, -1};
     } else {
+        // an isotropic unit direction and a finite step keep the position finite
         ++p.ndiff;
     }
-    if (!(m_finite(p.x[0]) && m_finite(p.x[1]) && m_finite(p.x[2]) && m_finite(p.E))) return Term{HIT_ESCAPED, -1};
     return Term{HIT_NONE, -1};
 }
 

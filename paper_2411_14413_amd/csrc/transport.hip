@@ -42,27 +42,83 @@ __device__ __forceinline__ void write_record(spx_record* rec, const SegDev<R>& s
     rec[s.first_rec + pid] = r;
 }
 
-// One flight of the lanes of this wave that are in state MODE.  When every such lane is
-// in the same segment the segment constants come through scalar loads.
-template <int MODE>
-__device__ __forceinline__ Term wave_step(const TransportArgs& a, const SegDev<float>* __restrict__ segs, int seg,
-                                          uint32_t pid, Particle<float>& p)
+// Per-lane bookkeeping of the batched kernel: counters of the lane's current segment,
+// flushed to the block's LDS counters (or HBM) when the lane moves to another segment.
+struct LaneAcc {
+    int seg = -1;
+    uint32_t c[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0};
+};
+
+struct BlockTally {
+    unsigned long long* lcnt;   // LDS per-segment counters (valid if a.lds_counters)
+    uint32_t* ltally;           // LDS tally (valid if a.lds_tally)
+};
+
+__device__ __forceinline__ void flush_acc(const TransportArgs& a, const BlockTally& bt, LaneAcc& acc)
 {
-    const int s0 = __builtin_amdgcn_readfirstlane(seg);
-    if (__ballot(seg != s0) == 0) return step_mode<float, MODE>(segs[s0], a.tab, a.k0, a.k1, pid, a.cap, p);
-    return step_mode<float, MODE>(segs[seg], a.tab, a.k0, a.k1, pid, a.cap, p);
+    if (acc.seg < 0) return;
+    if (a.lds_counters) {
+#pragma unroll
+        for (int i = 0; i < N_COUNTERS; ++i)
+            if (acc.c[i]) atomicAdd(&bt.lcnt[acc.seg * N_COUNTERS + i], (unsigned long long)acc.c[i]);
+    } else {
+        add_counters(a.counters + (size_t)acc.seg * N_COUNTERS, acc.c);
+    }
+#pragma unroll
+    for (int i = 0; i < N_COUNTERS; ++i) acc.c[i] = 0;
+}
+
+// End of a history: counters, tally, optional record; the lane becomes free.
+__device__ __forceinline__ void terminate(const TransportArgs& a, const BlockTally& bt, const SegDev<float>& s,
+                                          uint32_t pid, Particle<float>& p, const Term& t, LaneAcc& acc)
+{
+    // static indices only: the counters stay in registers
+    acc.c[C_DEPOSITED] += (t.state == HIT_DEPOSITED) ? 1u : 0u;
+    acc.c[C_WALL] += (t.state == HIT_WALL) ? 1u : 0u;
+    acc.c[C_ESCAPED] += (t.state == HIT_ESCAPED) ? 1u : 0u;
+    acc.c[C_COLLISIONS] += p.ncoll;
+    acc.c[C_DIFFUSIVE] += p.ndiff;
+    acc.c[C_THERMALIZED] += (p.st == ST_DIFFUSIVE) ? 1u : 0u;
+    if (t.state == HIT_DEPOSITED) {
+        const uint64_t b = s.bin_off + (uint64_t)t.bin;
+        if (a.lds_tally) atomicAdd(&bt.ltally[b], 1u);
+        else atomicAdd(&a.counts[b], 1ull);
+    }
+    if (a.records) write_record(a.records, s, pid, p, t);
+    p.st = ST_DEAD;
+}
+
+// Flights of the lanes in state MODE while the wave's situation allows: every such lane
+// in segment S (uniform, so its constants stay in scalar registers across the loop).
+// Leaves when the wave should refill, switch event kind, or has nothing left in MODE.
+template <int MODE>
+__device__ __forceinline__ void uniform_loop(const TransportArgs& a, const BlockTally& bt, const SegDev<float>& S,
+                                             uint32_t pid, Particle<float>& p, LaneAcc& acc, bool drained)
+{
+    for (;;) {
+        if (p.st == MODE) {
+            const Term t = step_mode<float, MODE>(S, a.tab, a.k0, a.k1, pid, a.cap, p);
+            if (t.state != HIT_NONE) terminate(a, bt, S, pid, p, t, acc);
+        }
+        const uint64_t M = __ballot(p.st == MODE);
+        if (M == 0) break;
+        if (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) break;
+        if (MODE == ST_BALLISTIC && __popcll(M) < a.ballistic_min && __ballot(p.st == ST_DIFFUSIVE) != 0) break;
+    }
 }
 
 // Dynamic LDS: per-segment counters (u64, when lds_counters) then the tally (u32, when lds_tally).
-__global__ void __launch_bounds__(1024) k_transport32(TransportArgs a, const SegDev<float>* __restrict__ segs)
+__global__ void __launch_bounds__(1024)
+k_transport32(TransportArgs a, const SegDev<float>* __restrict__ segs)
 {
     extern __shared__ unsigned long long lds[];
-    unsigned long long* lcnt = lds;
-    uint32_t* ltally = (uint32_t*)(lds + (a.lds_counters ? (size_t)a.n_seg * N_COUNTERS : 0));
+    BlockTally bt;
+    bt.lcnt = lds;
+    bt.ltally = (uint32_t*)(lds + (a.lds_counters ? (size_t)a.n_seg * N_COUNTERS : 0));
     if (a.lds_counters)
-        for (int i = threadIdx.x; i < a.n_seg * N_COUNTERS; i += blockDim.x) lcnt[i] = 0;
+        for (int i = threadIdx.x; i < a.n_seg * N_COUNTERS; i += blockDim.x) bt.lcnt[i] = 0;
     if (a.lds_tally)
-        for (uint32_t i = threadIdx.x; i < a.n_bins; i += blockDim.x) ltally[i] = 0;
+        for (uint32_t i = threadIdx.x; i < a.n_bins; i += blockDim.x) bt.ltally[i] = 0;
     __syncthreads();
 
     const int lane = threadIdx.x & 63;
@@ -72,22 +128,11 @@ __global__ void __launch_bounds__(1024) k_transport32(TransportArgs a, const Seg
     p.e = p.ndiff = p.ncoll = 0;
     uint32_t pid = 0;
     int seg = 0;
-    int acc_seg = -1;
-    uint32_t acc[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0};
+    LaneAcc acc;
     bool drained = false;   // wave-uniform: the ticket space is exhausted
 
-    auto flush_acc = [&]() {
-        if (acc_seg < 0) return;
-        if (a.lds_counters) {
-#pragma unroll
-            for (int i = 0; i < N_COUNTERS; ++i)
-                if (acc[i]) atomicAdd(&lcnt[acc_seg * N_COUNTERS + i], (unsigned long long)acc[i]);
-        } else {
-            add_counters(a.counters + (size_t)acc_seg * N_COUNTERS, acc);
-        }
-    };
-
     for (;;) {
+        // refill: one atomic claims tickets for all dead lanes (ballot + mbcnt prefix)
         const uint64_t dead = __ballot(p.st == ST_DEAD);
         const int n_dead = __popcll(dead);
         if (!drained && n_dead > 0 && (n_dead >= a.refill_min || n_dead == 64)) {
@@ -106,15 +151,13 @@ __global__ void __launch_bounds__(1024) k_transport32(TransportArgs a, const Seg
                     }
                     const int sg = (int)a.torder[lo];
                     pid = (uint32_t)(my - a.tfirst[lo]);
-                    if (sg != acc_seg) {
-                        flush_acc();
-#pragma unroll
-                        for (int i = 0; i < N_COUNTERS; ++i) acc[i] = 0;
-                        acc_seg = sg;
+                    if (sg != acc.seg) {
+                        flush_acc(a, bt, acc);
+                        acc.seg = sg;
                     }
                     seg = sg;
                     start(segs[seg], a.k0, a.k1, pid, p);
-                    acc[C_LAUNCHED] += 1;
+                    acc.c[C_LAUNCHED] += 1;
                 }
             }
         }
@@ -124,37 +167,32 @@ __global__ void __launch_bounds__(1024) k_transport32(TransportArgs a, const Seg
             if (drained) break;
             continue;
         }
-        // Run one kind of event per iteration: ballistic flights only once enough lanes are
-        // ballistic (or nothing else is left), so rare ballistic lanes do not drag the long
-        // collision path into most iterations of a thermalised wave.
+        // One kind of event at a time: ballistic flights only once enough lanes are
+        // ballistic (or nothing else is left), so that rare ballistic lanes do not drag the
+        // long collision path into most iterations of a thermalised wave.
         const int mode = (B != 0 && (__popcll(B) >= a.ballistic_min || D == 0)) ? ST_BALLISTIC : ST_DIFFUSIVE;
-        if (p.st == mode) {
-            const Term t = (mode == ST_BALLISTIC) ? wave_step<ST_BALLISTIC>(a, segs, seg, pid, p)
-                                                  : wave_step<ST_DIFFUSIVE>(a, segs, seg, pid, p);
-            if (t.state != HIT_NONE) {
-                const SegDev<float>& s = segs[seg];
-                acc[t.state == HIT_DEPOSITED ? C_DEPOSITED : (t.state == HIT_WALL ? C_WALL : C_ESCAPED)] += 1;
-                acc[C_COLLISIONS] += p.ncoll;
-                acc[C_DIFFUSIVE] += p.ndiff;
-                acc[C_THERMALIZED] += (p.st == ST_DIFFUSIVE) ? 1u : 0u;
-                if (t.state == HIT_DEPOSITED) {
-                    const uint64_t b = s.bin_off + (uint64_t)t.bin;
-                    if (a.lds_tally) atomicAdd(&ltally[b], 1u);
-                    else atomicAdd(&a.counts[b], 1ull);
-                }
-                if (a.records) write_record(a.records, s, pid, p, t);
-                p.st = ST_DEAD;
-            }
+        const uint64_t Mm = (mode == ST_BALLISTIC) ? B : D;
+        const int s0 = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)Mm) - 1);
+        if (__ballot(p.st == mode && seg != s0) == 0) {
+            const SegDev<float>& S = segs[s0];
+            if (mode == ST_BALLISTIC) uniform_loop<ST_BALLISTIC>(a, bt, S, pid, p, acc, drained);
+            else uniform_loop<ST_DIFFUSIVE>(a, bt, S, pid, p, acc, drained);
+        } else if (p.st == mode) {
+            // lanes of several segments: one flight with per-lane constants
+            const SegDev<float>& s = segs[seg];
+            const Term t = (mode == ST_BALLISTIC) ? step_mode<float, ST_BALLISTIC>(s, a.tab, a.k0, a.k1, pid, a.cap, p)
+                                                  : step_mode<float, ST_DIFFUSIVE>(s, a.tab, a.k0, a.k1, pid, a.cap, p);
+            if (t.state != HIT_NONE) terminate(a, bt, s, pid, p, t, acc);
         }
     }
-    flush_acc();
+    flush_acc(a, bt, acc);
     __syncthreads();
     if (a.lds_counters)
         for (int i = threadIdx.x; i < a.n_seg * N_COUNTERS; i += blockDim.x)
-            if (lcnt[i]) atomicAdd(&a.counters[i], lcnt[i]);
+            if (bt.lcnt[i]) atomicAdd(&a.counters[i], bt.lcnt[i]);
     if (a.lds_tally)
         for (uint32_t i = threadIdx.x; i < a.n_bins; i += blockDim.x)
-            if (ltally[i]) atomicAdd(&a.counts[i], (unsigned long long)ltally[i]);
+            if (bt.ltally[i]) atomicAdd(&a.counts[i], (unsigned long long)bt.ltally[i]);
 }
 
 __global__ void __launch_bounds__(256) k_transport64(const SegDev<double>* __restrict__ segp, TabDev<double> tab,
