@@ -40,7 +40,9 @@ METRIC = "particles/sec (and collisions/sec) at matched tally error, FP32 batche
 #   LAUNCH: two Philox blocks (312), truncated-normal inverse CDF (35), Thompson
 #           inverse CDF (10), cosine direction and frame rotations (43)
 OPS = dict(FLIGHT=279, LAMBDA=60, COLLIDE=321, DIFFDIR=20, LAUNCH=400)
-PEAK_ALU = 256 * 64 * 2.4e9          # lane-slots/s: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
+# Peak: the FP32 vector rate of the MI355X, 157.3 TFLOP/s = 78.6e12 FMA/s, i.e. 128 lanes per
+# CU per clock (256 CUs, 2.4 GHz); one slot = one full-rate 32-bit lane operation.
+PEAK_ALU = 256 * 128 * 2.4e9
 
 
 def algorithmic_ops(counters):
@@ -186,8 +188,9 @@ def main():
     roofline = dict(bound="alu", kernel="k_transport32", achieved=achieved / 1e12, peak=PEAK_ALU / 1e12,
                     unit="TOP/s", frac=achieved / PEAK_ALU, traffic=None,
                     ops_per_launch=ops, launch_ms=ms_med,
-                    note="VALU issue slots per lane counted from the algorithm; peak = 256 CU x 64 lanes x 2.4 GHz; "
-                         "launch time = HIP-event time of the graph replay (zero + transport + normalise)")
+                    note="VALU issue slots per lane counted from the algorithm (quarter-rate ops = 4 slots); "
+                         "peak = 256 CU x 128 lanes x 2.4 GHz (the FP32 vector rate); launch time = HIP-event time "
+                         "of the graph replay (zero + transport + normalise)")
 
     result = {
         "metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,

@@ -446,13 +446,21 @@ static int run(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters,
 static int autotune(Plan* P, hipStream_t st)
 {
     const int n = P->n_seg;
-    const uint64_t per_seg_target = std::max<uint64_t>(4096, (uint64_t)(3.0e6 / n));
+    // The tuning sample keeps the plan's mix: the same fraction of every segment, sized so
+    // that each resident lane gets ~16 histories (a persistent launch's tail depends on it).
+    int bpc_max = 0;
+    SPX_TRY(occupancy_transport32(P, 256, &bpc_max));
+    const double lanes = (double)std::max(1, bpc_max) * P->n_cu * 256.0;
+    const double frac = std::min(1.0, 16.0 * lanes / (double)std::max<uint64_t>(1, P->n_particles_total));
     std::vector<uint64_t> tf(n + 1, 0);
     std::vector<uint32_t> order(n);
     std::iota(order.begin(), order.end(), 0u);
     std::stable_sort(order.begin(), order.end(),
                      [&](uint32_t a, uint32_t b) { return P->seg[a].pressure > P->seg[b].pressure; });
-    for (int o = 0; o < n; ++o) tf[o + 1] = tf[o] + std::min<uint64_t>(P->seg[order[o]].N, per_seg_target);
+    for (int o = 0; o < n; ++o) {
+        const uint64_t Nk = P->seg[order[o]].N;
+        tf[o + 1] = tf[o] + std::min<uint64_t>(Nk, (uint64_t)std::ceil(frac * (double)Nk));
+    }
     uint64_t *d_tf = nullptr, *d_counts = nullptr, *d_ctr = nullptr;
     SPX_TRY(dalloc(&d_tf, n + 1));
     int rc = dalloc(&d_counts, P->n_bins_total);
@@ -464,7 +472,7 @@ static int autotune(Plan* P, hipStream_t st)
     float best = 1e30f;
     int bb = P->blocks, bt = P->threads, br = P->refill_min, bm = P->ballistic_min;
     const int thread_opts[] = {256, 512, 1024};
-    const int mode_opts[][2] = {{1, 1}, {8, 8}, {16, 16}, {16, 32}, {32, 32}};
+    const int mode_opts[][2] = {{4, 4}, {8, 8}, {16, 16}};
     for (int t : thread_opts) {
         if (rc != SPX_OK) break;
         int bpc = 0;
