@@ -231,68 +231,50 @@ struct HitF {
 
 // Nearest surface with 0 < t <= ell; exact ties keep substrate, then cathode, then chamber.
 // Planes use the precomputed n.c, u.c, v.c: t = (n.c - n.x)/(n.d), q.u = u.x + t u.d - u.c.
+// Written without branches (every candidate computed, then selected) so that the whole
+// test is one basic block: a wave runs it once whatever its lanes need, and the loads of
+// the surface constants can be scheduled early.  A direction parallel to a plane gives a
+// reciprocal of zero, hence t = inf or NaN, which fails t > 0 as intended.
 template <typename R>
 __device__ __forceinline__ HitF hit_test(const SegDev<R>& s, const R* x, const R* d, R ell, R& t_hit, R& qu_hit,
                                          R& qv_hit, bool first)
 {
-    R best = m_inf<R>();
-    int state = HIT_NONE;
-    {   // substrate plate
-        const R dn = dot3(d, s.sub_n);
-        if (dn != (R)0) {
-            const R t = (s.sub_nc - dot3(x, s.sub_n)) * m_rcp(dn);
-            if (t > (R)0) {
-                const R qu = dot3(x, s.sub_u) + t * dot3(d, s.sub_u) - s.sub_uc;
-                const R qv = dot3(x, s.sub_v) + t * dot3(d, s.sub_v) - s.sub_vc;
-                const bool inside = (s.shape == 0) ? (fabs(qu) <= s.half_u && fabs(qv) <= s.half_v)
-                                                   : (qu * qu + qv * qv <= s.sub_R2);
-                if (inside) {
-                    best = t;
-                    qu_hit = qu;
-                    qv_hit = qv;
-                    state = (dn < (R)0) ? HIT_DEPOSITED : HIT_WALL;
-                }
-            }
-        }
-    }
+    const R inf = m_inf<R>();
+    // substrate plate: the front face (moving against its normal) deposits
+    const R dn = dot3(d, s.sub_n);
+    const R ts = (s.sub_nc - dot3(x, s.sub_n)) * m_rcp(dn);
+    const R qu = dot3(x, s.sub_u) + ts * dot3(d, s.sub_u) - s.sub_uc;
+    const R qv = dot3(x, s.sub_v) + ts * dot3(d, s.sub_v) - s.sub_vc;
+    const bool in_s = (s.shape == 0) ? (fabs(qu) <= s.half_u && fabs(qv) <= s.half_v) : (qu * qu + qv * qv <= s.sub_R2);
+    const bool hit_s = (ts > (R)0) && in_s;
+    R best = hit_s ? ts : inf;
+    int state = hit_s ? (dn < (R)0 ? HIT_DEPOSITED : HIT_WALL) : HIT_NONE;
+    qu_hit = qu;
+    qv_hit = qv;
     // emitting cathode disc (both faces absorb).  The first flight starts on the target
     // plane and a line meets a plane once, so on that flight the target is not tested.
-    if (!first) {
-        const R dn = dot3(d, s.cat_n);
-        if (dn != (R)0) {
-            const R t = (s.cat_nc - dot3(x, s.cat_n)) * m_rcp(dn);
-            if (t > (R)0 && t < best) {
-                const R qu = dot3(x, s.cat_u) + t * dot3(d, s.cat_u) - s.cat_uc;
-                const R qv = dot3(x, s.cat_v) + t * dot3(d, s.cat_v) - s.cat_vc;
-                if (qu * qu + qv * qv <= s.cat_R2) {
-                    best = t;
-                    state = HIT_WALL;
-                }
-            }
-        }
-    }
-    {   // chamber: cylinder side and caps
-        R tc = m_inf<R>();
-        const R a = d[0] * d[0] + d[1] * d[1];
-        if (a > (R)0) {
-            const R b = x[0] * d[0] + x[1] * d[1];
-            const R c = x[0] * x[0] + x[1] * x[1] - s.ch_R2;
-            R disc = b * b - a * c;
-            disc = disc > (R)0 ? disc : (R)0;
-            const R sq = m_sqrt(disc);
-            R t = (b <= (R)0) ? (sq - b) * m_rcp(a) : -c * m_rcp(b + sq);
-            tc = t > (R)0 ? t : (R)0;
-        }
-        if (d[2] != (R)0) {
-            R t = ((d[2] > (R)0 ? s.zhi : s.zlo) - x[2]) * m_rcp(d[2]);
-            t = t > (R)0 ? t : (R)0;
-            tc = t < tc ? t : tc;
-        }
-        if (tc < best) {
-            best = tc;
-            state = HIT_WALL;
-        }
-    }
+    const R dc = dot3(d, s.cat_n);
+    const R tcat = (s.cat_nc - dot3(x, s.cat_n)) * m_rcp(dc);
+    const R cu = dot3(x, s.cat_u) + tcat * dot3(d, s.cat_u) - s.cat_uc;
+    const R cv = dot3(x, s.cat_v) + tcat * dot3(d, s.cat_v) - s.cat_vc;
+    const bool hit_c = !first && (tcat > (R)0) && (tcat < best) && (cu * cu + cv * cv <= s.cat_R2);
+    best = hit_c ? tcat : best;
+    state = hit_c ? HIT_WALL : state;
+    // chamber: cylinder side (stable root of |x + t d|^2 = R^2 in the xy-plane) and caps
+    const R a = d[0] * d[0] + d[1] * d[1];
+    const R b = x[0] * d[0] + x[1] * d[1];
+    const R c = x[0] * x[0] + x[1] * x[1] - s.ch_R2;
+    R disc = b * b - a * c;
+    disc = disc > (R)0 ? disc : (R)0;
+    const R sq = m_sqrt(disc);
+    R tside = (b <= (R)0) ? (sq - b) * m_rcp(a) : -c * m_rcp(b + sq);
+    tside = (a > (R)0) ? (tside > (R)0 ? tside : (R)0) : inf;
+    R tcap = ((d[2] > (R)0 ? s.zhi : s.zlo) - x[2]) * m_rcp(d[2]);
+    tcap = (d[2] != (R)0) ? (tcap > (R)0 ? tcap : (R)0) : inf;
+    const R tch = tcap < tside ? tcap : tside;
+    const bool hit_w = tch < best;
+    best = hit_w ? tch : best;
+    state = hit_w ? HIT_WALL : state;
     if (!(best <= ell)) state = HIT_NONE;
     t_hit = best;
     return HitF{state};

@@ -69,6 +69,7 @@ struct TransportArgs {
 };
 
 constexpr size_t LDS_COUNTERS_MAX = 16384;   // bytes: up to 292 segments
+constexpr uint64_t TICKET_CHUNK = 64;        // tickets a wave claims per global atomic
 constexpr size_t LDS_TALLY_MAX = 49152;      // bytes: up to 12288 bins
 
 struct GraphKey {

@@ -130,20 +130,34 @@ k_transport32(TransportArgs a, const SegDev<float>* __restrict__ segs)
     int seg = 0;
     LaneAcc acc;
     bool drained = false;   // wave-uniform: the ticket space is exhausted
+    // Wave-private run of tickets [tk, tk_end), claimed TICKET_CHUNK at a time with one
+    // atomic, so that refills rarely touch the global counter.
+    uint64_t tk = 0, tk_end = 0;
 
     for (;;) {
-        // refill: one atomic claims tickets for all dead lanes (ballot + mbcnt prefix)
+        // refill: dead lanes take consecutive tickets of the wave's run (ballot + mbcnt prefix)
         const uint64_t dead = __ballot(p.st == ST_DEAD);
         const int n_dead = __popcll(dead);
         if (!drained && n_dead > 0 && (n_dead >= a.refill_min || n_dead == 64)) {
-            const int leader = __ffsll((unsigned long long)dead) - 1;
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd((unsigned long long*)a.ticket, (unsigned long long)n_dead);
-            base = __shfl(base, leader);
-            if (base + (uint64_t)n_dead >= a.total) drained = true;
+            if (tk == tk_end) {
+                unsigned long long base = 0;
+                if (lane == 0) base = atomicAdd((unsigned long long*)a.ticket, (unsigned long long)TICKET_CHUNK);
+                base = __shfl(base, 0);
+                if (base >= a.total) {
+                    drained = true;
+                } else {
+                    tk = base;
+                    tk_end = (base + TICKET_CHUNK < a.total) ? base + TICKET_CHUNK : a.total;
+                }
+            }
+            const uint64_t avail = tk_end - tk;
+            const uint64_t take = avail < (uint64_t)n_dead ? avail : (uint64_t)n_dead;
+            const uint64_t base = tk;
+            tk += take;
             if (p.st == ST_DEAD) {
-                const uint64_t my = base + (uint64_t)__popcll(dead & lt_mask);
-                if (my < a.total) {
+                const uint64_t rank = (uint64_t)__popcll(dead & lt_mask);
+                const uint64_t my = base + rank;
+                if (rank < take) {
                     int lo = 0, hi = a.n_seg;
                     while (hi - lo > 1) {
                         const int mid = (lo + hi) >> 1;
