@@ -280,6 +280,32 @@ __device__ __forceinline__ HitF hit_test(const SegDev<R>& s, const R* x, const R
     return HitF{state};
 }
 
+// Distance from x to the nearest absorbing surface the surface test knows (never more than
+// the true distance): the substrate plate and the target disc as point-to-region
+// distances, the chamber side and caps.  A path that stays closer to x than this cannot
+// meet any surface.
+template <typename R> __device__ __forceinline__ R clearance(const SegDev<R>& s, const R* x)
+{
+    const R h = dot3(x, s.sub_n) - s.sub_nc;
+    const R qu = dot3(x, s.sub_u) - s.sub_uc, qv = dot3(x, s.sub_v) - s.sub_vc;
+    R e2;
+    if (s.shape == 0) {
+        const R eu = fmax(fabs(qu) - s.half_u, (R)0), ev = fmax(fabs(qv) - s.half_v, (R)0);
+        e2 = eu * eu + ev * ev;
+    } else {
+        const R er = fmax(m_sqrt(qu * qu + qv * qv) - m_sqrt(s.sub_R2), (R)0);
+        e2 = er * er;
+    }
+    const R d_sub2 = h * h + e2;
+    const R hc = dot3(x, s.cat_n) - s.cat_nc;
+    const R cu = dot3(x, s.cat_u) - s.cat_uc, cv = dot3(x, s.cat_v) - s.cat_vc;
+    const R ec = fmax(m_sqrt(cu * cu + cv * cv) - m_sqrt(s.cat_R2), (R)0);
+    const R d_cat2 = hc * hc + ec * ec;
+    const R side = m_sqrt(s.ch_R2) - m_sqrt(x[0] * x[0] + x[1] * x[1]);
+    const R caps = fmin(x[2] - s.zlo, s.zhi - x[2]);
+    return fmin(m_sqrt(fmin(d_sub2, d_cat2)), fmin(side, caps));
+}
+
 // Tally bin of a deposit at in-plane coordinates (qu, qv) of the substrate (clamped).
 template <typename R> __device__ __forceinline__ int tally_bin(const SegDev<R>& s, R qu, R qv)
 {
@@ -374,6 +400,7 @@ template <typename R> __device__ __forceinline__ void kahan_add(R& s, R& c, R v)
 // Per-particle dynamic state.
 template <typename R> struct Particle {
     R x[3], xc[3], d[3], E;   // position = x - xc (compensated)
+    R r2;              // batched FP32 diffusive mode: squared clearance-ball radius (d = centre)
     uint32_t e;        // flights taken
     uint32_t ndiff;    // diffusive steps ended in the gas
     uint32_t ncoll;    // ballistic collisions
@@ -416,12 +443,68 @@ __device__ __forceinline__ Term step_mode(const SegDev<R>& s, const TabDev<R>& t
         if (s.gas_motion) gas_velocity(s, philox4x32_10(make_uint4(pid, e, s.cfgcat, 1u), k0, k1), V);
         collide(s, tb, p.E, p.d, V, u01<R>(r.y), u01<R>(r.z));
         ++p.ncoll;
-        if (p.E <= s.E_th) p.st = ST_DIFFUSIVE;
+        if (p.E <= s.E_th) {
+            p.st = ST_DIFFUSIVE;
+            p.r2 = (R)-1;      // no clearance ball yet: the first diffusive step is tested
+        }
         if (!(m_finite(p.x[0]) && m_finite(p.x[1]) && m_finite(p.x[2]) && m_finite(p.E)))
             return Term{HIT_ESCAPED, -1};
     } else {
         // an isotropic unit direction and a finite step keep the position finite
         ++p.ndiff;
+    }
+    return Term{HIT_NONE, -1};
+}
+
+// Slack between the clearance and the ball radius [mm]: far above the FP32 rounding of the
+// position and of the surface test at chamber sizes up to metres.
+constexpr float CLEAR_MARGIN = 0.02f;
+
+// One diffusive step of the batched FP32 path (event p.e + 1).  The direction is drawn
+// afresh every step, so in this mode p.d holds the centre of a clearance ball and p.r2 its
+// squared radius: the anchor's clearance less CLEAR_MARGIN.  A step that ends strictly
+// inside the ball (a convex set, entered at its start) stays more than CLEAR_MARGIN away
+// from every surface, so the surface test would find nothing and is skipped.  Otherwise the
+// step is tested as usual and, if it ends in the gas, the ball is rebuilt around its end.
+// Outcome and arithmetic are those of the tested step.
+__device__ __forceinline__ Term step_diffusive_ball(const SegDev<float>& s, uint32_t k0, uint32_t k1, uint32_t pid,
+                                                    uint32_t cap, Particle<float>& p)
+{
+    if (p.e >= cap) return Term{HIT_ESCAPED, -1};
+    const uint32_t e = p.e + 1;
+    p.e = e;
+    const uint4 r = philox4x32_10(make_uint4(pid, e, s.cfgcat, 0u), k0, k1);
+    float dir[3];
+    const float ell = s.vacuum ? m_inf<float>() : diffusive_draw(s, r, dir);
+    // the compensated move, not yet committed (kahan_add split in two)
+    float y[3], t[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        y[i] = ell * dir[i] - p.xc[i];
+        t[i] = p.x[i] + y[i];
+    }
+    const float q0 = t[0] - p.d[0], q1 = t[1] - p.d[1], q2 = t[2] - p.d[2];
+    const bool inside = q0 * q0 + q1 * q1 + q2 * q2 < p.r2;   // false for NaN / infinite steps
+    if (!inside) {
+        float th, qu = 0.f, qv = 0.f;
+        const HitF h = hit_test(s, p.x, dir, ell, th, qu, qv, false);
+        if (h.state != HIT_NONE) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) kahan_add(p.x[i], p.xc[i], th * dir[i]);
+            return Term{h.state, h.state == HIT_DEPOSITED ? tally_bin(s, qu, qv) : -1};
+        }
+        if (!(ell < m_inf<float>())) return Term{HIT_ESCAPED, -1};
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        p.xc[i] = (t[i] - p.x[i]) - y[i];
+        p.x[i] = t[i];
+    }
+    ++p.ndiff;
+    if (!inside) {
+        const float c = clearance(s, p.x) - CLEAR_MARGIN;
+        p.d[0] = p.x[0]; p.d[1] = p.x[1]; p.d[2] = p.x[2];
+        p.r2 = c > 0.f ? c * c : -1.f;
     }
     return Term{HIT_NONE, -1};
 }
@@ -441,6 +524,7 @@ __device__ __forceinline__ void start(const SegDev<R>& s, uint32_t k0, uint32_t 
     const uint4 r1 = philox4x32_10(make_uint4(pid, 0u, s.cfgcat, 1u), k0, k1);
     launch(s, r0, r1, p.x, p.d, p.E);
     p.xc[0] = p.xc[1] = p.xc[2] = (R)0;
+    p.r2 = (R)-1;
     p.e = 0;
     p.ndiff = 0;
     p.ncoll = 0;

@@ -97,7 +97,8 @@ __device__ __forceinline__ void uniform_loop(const TransportArgs& a, const Block
 {
     for (;;) {
         if (p.st == MODE) {
-            const Term t = step_mode<float, MODE>(S, a.tab, a.k0, a.k1, pid, a.cap, p);
+            const Term t = (MODE == ST_BALLISTIC) ? step_mode<float, ST_BALLISTIC>(S, a.tab, a.k0, a.k1, pid, a.cap, p)
+                                                  : step_diffusive_ball(S, a.k0, a.k1, pid, a.cap, p);
             if (t.state != HIT_NONE) terminate(a, bt, S, pid, p, t, acc);
         }
         const uint64_t M = __ballot(p.st == MODE);
@@ -108,7 +109,9 @@ __device__ __forceinline__ void uniform_loop(const TransportArgs& a, const Block
 }
 
 // Dynamic LDS: per-segment counters (u64, when lds_counters) then the tally (u32, when lds_tally).
-__global__ void __launch_bounds__(1024)
+// At most 96 VGPRs: five waves per SIMD hide the latency of the transcendental and
+// integer-multiply chains.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5)))
 k_transport32(TransportArgs a, const SegDev<float>* __restrict__ segs)
 {
     extern __shared__ unsigned long long lds[];
@@ -195,7 +198,7 @@ k_transport32(TransportArgs a, const SegDev<float>* __restrict__ segs)
             // lanes of several segments: one flight with per-lane constants
             const SegDev<float>& s = segs[seg];
             const Term t = (mode == ST_BALLISTIC) ? step_mode<float, ST_BALLISTIC>(s, a.tab, a.k0, a.k1, pid, a.cap, p)
-                                                  : step_mode<float, ST_DIFFUSIVE>(s, a.tab, a.k0, a.k1, pid, a.cap, p);
+                                                  : step_diffusive_ball(s, a.k0, a.k1, pid, a.cap, p);
             if (t.state != HIT_NONE) terminate(a, bt, s, pid, p, t, acc);
         }
     }
