@@ -39,7 +39,24 @@ METRIC = "particles/sec (and collisions/sec) at matched tally error, FP32 batche
 #   DIFFDIR: isotropic direction (20)
 #   LAUNCH: two Philox blocks (312), truncated-normal inverse CDF (35), Thompson
 #           inverse CDF (10), cosine direction and frame rotations (43)
-OPS = dict(FLIGHT=279, LAMBDA=60, COLLIDE=321, DIFFDIR=20, LAUNCH=400)
+# VALU issue slots per lane of each unit of work, counted from the formulas the kernel
+# evaluates: a 32x32->64 multiply and a native transcendental take 4 slots, any other FP32 or
+# 32-bit integer operation 1.  Philox4x32-10 block: 10 rounds x (2 multiplies + 2 three-input
+# XORs) = 100 (the key schedule is wave-uniform, scalar); a uniform from a word: 3.
+PHILOX, U01 = 100, 3
+OPS = dict(
+    # 2 blocks, 5 uniforms; truncated-normal inverse CDF, Thompson energy, cosine direction, frame
+    LAUNCH=2 * PHILOX + 5 * U01 + 95,
+    # block, 3 uniforms, lambda_m (table + Maxwellian mean speed) 60, free path 6, surface test
+    # 100, compensated move 15, event bookkeeping 2
+    BALLISTIC=PHILOX + 3 * U01 + 60 + 6 + 100 + 15 + 2,
+    # gas-velocity block and 4 uniforms, Box-Muller 40, kinematics with the table lookup 130
+    COLLIDE=PHILOX + 4 * U01 + 40 + 130,
+    # block, 3 uniforms, isotropic direction and exponential length 24, step vector 3,
+    # compensated move 12, clearance-ball test 7, bookkeeping 2, plus 2 for the ~1.3 % of steps
+    # that leave the ball and take the surface test and a new clearance (~150 slots)
+    DIFFUSIVE=PHILOX + 3 * U01 + 24 + 3 + 12 + 7 + 2 + 2,
+)
 # Peak: the FP32 vector rate of the MI355X, 157.3 TFLOP/s = 78.6e12 FMA/s, i.e. 128 lanes per
 # CU per clock (256 CUs, 2.4 GHz); one slot = one full-rate 32-bit lane operation.
 PEAK_ALU = 256 * 128 * 2.4e9
@@ -51,11 +68,10 @@ def algorithmic_ops(counters):
     coll = counters[:, 4].sum()
     diff = counters[:, 5].sum()
     therm = counters[:, 6].sum()
-    flights = N + coll + diff
-    ballistic_flights = coll + (N - therm)
-    diffusive_flights = diff + therm
-    return float(N * OPS["LAUNCH"] + flights * OPS["FLIGHT"] + ballistic_flights * OPS["LAMBDA"] +
-                 coll * OPS["COLLIDE"] + diffusive_flights * OPS["DIFFDIR"])
+    ballistic_flights = coll + (N - therm)     # every collision, plus the last flight of atoms never thermalised
+    diffusive_steps = diff + therm             # every diffusive step, plus the last step of thermalised atoms
+    return float(N * OPS["LAUNCH"] + ballistic_flights * OPS["BALLISTIC"] + coll * OPS["COLLIDE"] +
+                 diffusive_steps * OPS["DIFFUSIVE"])
 
 
 def workload(name, scale=1.0):

@@ -53,6 +53,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         L.or_philox4x32_10.argtypes = [_u32p, _u32p, _u32p]
         L.or_philox_batch.argtypes = [_u32p, ctypes.c_int64, _u32p, _u32p]
+        L.or_diffusive_uniforms.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, _dp]
         L.or_u01.argtypes = [ctypes.c_uint32]
         L.or_u01.restype = ctypes.c_double
         L.or_norm_cdf.argtypes = [ctypes.c_double]
@@ -122,6 +123,13 @@ def philox_batch(ctr, key) -> np.ndarray:
 
 def u01(x: int) -> float:
     return lib().or_u01(int(x))
+
+
+def diffusive_uniforms(seed: int, pid: int, event: int, cfgcat: int) -> np.ndarray:
+    """The three RN of diffusive step `event` (two steps per Philox block, 21-bit RN)."""
+    out = np.empty(3)
+    lib().or_diffusive_uniforms(seed, pid, event, cfgcat, _p(out))
+    return out
 
 
 def norm_inv(p: float) -> float:

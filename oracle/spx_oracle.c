@@ -91,6 +91,27 @@ static void draw4(uint64_t seed, uint32_t pid, uint32_t event, uint32_t cfgcat, 
     for (int i = 0; i < 4; ++i) u[i] = or_u01(x[i]);
 }
 
+/* The three RN of diffusive step `event` (direction cosine, azimuth, length).  A diffusive
+ * step needs 3 RN, so two steps share one Philox block: steps 2m and 2m+1 use block
+ * (pid, 2m, cfgcat, 2).  The even step takes the top 21 bits of words 0, 1, 2; the odd step
+ * takes the low 11 bits of word i followed by bits [10 i, 10 i + 10) of word 3, i = 0, 1, 2.
+ * RN = (k + 1) 2^-21 on ]0,1] for a 21-bit k. */
+void or_diffusive_uniforms(uint64_t seed, uint32_t pid, uint32_t event, uint32_t cfgcat, double u[3])
+{
+    uint32_t ctr[4] = {pid, event & ~1u, cfgcat, 2u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    or_philox4x32_10(ctr, key, x);
+    for (int i = 0; i < 3; ++i) {
+        uint32_t k;
+        if (event & 1u)
+            k = ((x[i] & 0x7FFu) << 10) | ((x[3] >> (10 * i)) & 0x3FFu);
+        else
+            k = x[i] >> 11;
+        u[i] = (double)(k + 1u) * (1.0 / 2097152.0);
+    }
+}
+
 /* ------------------------------------------------------------------------- */
 /* Normal distribution: CDF via erfc, inverse CDF via Wichura's AS241 (PPND16). */
 /* ------------------------------------------------------------------------- */
@@ -619,8 +640,8 @@ static void gas_velocity(const seg_t* s, const double w[4], double V[3])
     V[2] = s->vth * r1 * cos(2.0 * OR_PI * w[3]);
 }
 
-/* Isotropic direction and exponential step of a thermalised atom. */
-static void diffusive_draw(const seg_t* s, const double u[4], double d[3], double* ell)
+/* Isotropic direction and exponential step of a thermalised atom from its three RN. */
+static void diffusive_draw(const seg_t* s, const double u[3], double d[3], double* ell)
 {
     const double mu = 2.0 * u[1] - 1.0;
     const double st = sqrt(1.0 - mu * mu);
@@ -653,11 +674,12 @@ static void trace(const seg_t* s, const tab_t* tb, uint64_t seed, uint32_t pid, 
     for (;; ++e) {
         if (e > tb->event_cap) { res->state = OR_ESCAPED; e = tb->event_cap; break; }
         double u[4];
-        draw4(seed, pid, e, s->cfgcat, 0, u);
         double ell;
         if (!diffusive) {
+            draw4(seed, pid, e, s->cfgcat, 0, u);
             ell = flight_length(s, tb, E, u[0]);
         } else {
+            or_diffusive_uniforms(seed, pid, e, s->cfgcat, u);
             diffusive_draw(s, u, d, &ell);
         }
         hit_t h = hit_test(s, x, d, ell, e == 1);
@@ -900,8 +922,8 @@ void or_walk(const double* seg, const double* prm, const double* theta, const do
     seg_init(seg, prm, &tb, &s);
     double x[3] = {0.0, 0.0, 0.0};
     for (uint32_t e = 1; e <= n_steps; ++e) {
-        double u[4], d[3], ell;
-        draw4(seed, pid, e, s.cfgcat, 0, u);
+        double u[3], d[3], ell;
+        or_diffusive_uniforms(seed, pid, e, s.cfgcat, u);
         diffusive_draw(&s, u, d, &ell);
         for (int i = 0; i < 3; ++i) x[i] += ell * d[i];
     }

@@ -16,6 +16,10 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-Wall",
     # no packed FP32 instructions: plain VALU FP32 everywhere
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # a*b+c fuses only within one source expression, never across statements: every inlined
+    # copy of a device function rounds the same way, so a particle's history does not
+    # depend on which code path (launch shape, wave state) ran it
+    "-ffp-contract=on",
 ]
 
 

@@ -447,11 +447,13 @@ static int autotune(Plan* P, hipStream_t st)
 {
     const int n = P->n_seg;
     // The tuning sample keeps the plan's mix: the same fraction of every segment, sized so
-    // that each resident lane gets ~16 histories (a persistent launch's tail depends on it).
+    // that each resident lane gets ~48 histories: a persistent launch ends in a tail of the longest
+    // histories whose share of the time shrinks with the work per lane, and a sample with too
+    // little work per lane favours shapes that only shorten that tail.
     int bpc_max = 0;
     SPX_TRY(occupancy_transport32(P, 256, &bpc_max));
     const double lanes = (double)std::max(1, bpc_max) * P->n_cu * 256.0;
-    const double frac = std::min(1.0, 16.0 * lanes / (double)std::max<uint64_t>(1, P->n_particles_total));
+    const double frac = std::min(1.0, 48.0 * lanes / (double)std::max<uint64_t>(1, P->n_particles_total));
     std::vector<uint64_t> tf(n + 1, 0);
     std::vector<uint32_t> order(n);
     std::iota(order.begin(), order.end(), 0u);

@@ -56,6 +56,37 @@ template <> __device__ __forceinline__ double u01<double>(uint32_t x)
     return (double)((x >> 8) + 1u) * 0x1p-24;
 }
 
+// RN in ]0,1] from a 21-bit code k: (k + 1) * 2^-21, exact in float and double.
+template <typename R> __device__ __forceinline__ R u21(uint32_t k);
+template <> __device__ __forceinline__ float u21<float>(uint32_t k)
+{
+    return __builtin_fmaf((float)k, 0x1p-21f, 0x1p-21f);
+}
+template <> __device__ __forceinline__ double u21<double>(uint32_t k)
+{
+    return (double)(k + 1u) * 0x1p-21;
+}
+
+// A diffusive step needs three RN, so steps 2m and 2m+1 share the Philox block
+// (pid, 2m, cfgcat, 2): the even step takes the top 21 bits of words x, y, z; the odd step
+// the low 11 bits of word i followed by bits [10 i, 10 i + 10) of word w.
+__device__ __forceinline__ uint4 diffusive_block(uint32_t pid, uint32_t e, uint32_t cfgcat, uint32_t k0, uint32_t k1)
+{
+    return philox4x32_10(make_uint4(pid, e & ~1u, cfgcat, 2u), k0, k1);
+}
+__device__ __forceinline__ void diffusive_codes(uint4 w, bool odd, uint32_t* k)
+{
+    if (odd) {
+        k[0] = ((w.x & 0x7FFu) << 10) | (w.w & 0x3FFu);
+        k[1] = ((w.y & 0x7FFu) << 10) | ((w.w >> 10) & 0x3FFu);
+        k[2] = ((w.z & 0x7FFu) << 10) | ((w.w >> 20) & 0x3FFu);
+    } else {
+        k[0] = w.x >> 11;
+        k[1] = w.y >> 11;
+        k[2] = w.z >> 11;
+    }
+}
+
 // --------------------------------------------------------------------------
 // Math overloads for R.
 // --------------------------------------------------------------------------
@@ -372,11 +403,12 @@ __device__ __forceinline__ void collide(const SegDev<R>& s, const TabDev<R>& tb,
     }
 }
 
-// Isotropic direction and exponential step of a thermalised atom (sub-block 0 of the event).
+// Isotropic direction and exponential step of a thermalised atom from its three 21-bit codes
+// (length, direction cosine, azimuth).
 template <typename R>
-__device__ __forceinline__ R diffusive_draw(const SegDev<R>& s, uint4 r, R* d)
+__device__ __forceinline__ R diffusive_draw(const SegDev<R>& s, const uint32_t* k, R* d)
 {
-    const R u0 = u01<R>(r.x), u1 = u01<R>(r.y), u2 = u01<R>(r.z);
+    const R u0 = u21<R>(k[0]), u1 = u21<R>(k[1]), u2 = u21<R>(k[2]);
     const R mu = (R)2 * u1 - (R)1;
     const R st = m_sqrt(((R)1 - mu) * ((R)1 + mu));
     R sp, cp;
@@ -421,12 +453,15 @@ __device__ __forceinline__ Term step_mode(const SegDev<R>& s, const TabDev<R>& t
     if (p.e >= cap) return Term{HIT_ESCAPED, -1};
     const uint32_t e = p.e + 1;
     p.e = e;
-    const uint4 r = philox4x32_10(make_uint4(pid, e, s.cfgcat, 0u), k0, k1);
+    uint4 r = make_uint4(0u, 0u, 0u, 0u);
     R ell;
     if (MODE == ST_BALLISTIC) {
+        r = philox4x32_10(make_uint4(pid, e, s.cfgcat, 0u), k0, k1);
         ell = s.vacuum ? m_inf<R>() : -lambda_m(s, tb, p.E) * m_log(u01<R>(r.x));
     } else {
-        ell = s.vacuum ? m_inf<R>() : diffusive_draw(s, r, p.d);
+        uint32_t k[3];
+        diffusive_codes(diffusive_block(pid, e, s.cfgcat, k0, k1), (e & 1u) != 0, k);
+        ell = s.vacuum ? m_inf<R>() : diffusive_draw(s, k, p.d);
     }
     R t, qu = (R)0, qv = (R)0;
     const HitF h = hit_test(s, p.x, p.d, ell, t, qu, qv, e == 1u);
@@ -456,6 +491,42 @@ __device__ __forceinline__ Term step_mode(const SegDev<R>& s, const TabDev<R>& t
     return Term{HIT_NONE, -1};
 }
 
+// The diffusive move split so that two walks can share it bit for bit: the step vector
+// v = ell d, then the compensated add of v (kahan_try forms the candidate t, kahan_commit
+// accepts it).  Every operation is rounded on its own (no contraction into fused
+// multiply-adds), so the step-by-step walk and the wave-cooperative walk, which forms v in
+// one lane and the sums in another, produce identical positions.
+__device__ __forceinline__ void step_vector(float ell, const float* dir, float* v)
+{
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) v[i] = ell * dir[i];
+}
+__device__ __forceinline__ void kahan_try(const float* x, const float* xc, const float* v, float* y, float* t)
+{
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        y[i] = v[i] - xc[i];
+        t[i] = x[i] + y[i];
+    }
+}
+__device__ __forceinline__ void kahan_commit(float* x, float* xc, const float* y, const float* t)
+{
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        xc[i] = (t[i] - x[i]) - y[i];
+        x[i] = t[i];
+    }
+}
+// t strictly inside the ball of squared radius r2 around c (false for NaN and infinities)
+__device__ __forceinline__ bool ball_holds(const float* t, const float* c, float r2)
+{
+    const float q0 = t[0] - c[0], q1 = t[1] - c[1], q2 = t[2] - c[2];
+    return __builtin_fmaf(q2, q2, __builtin_fmaf(q1, q1, q0 * q0)) < r2;
+}
+
 // Slack between the clearance and the ball radius [mm]: far above the FP32 rounding of the
 // position and of the surface test at chamber sizes up to metres.
 constexpr float CLEAR_MARGIN = 0.02f;
@@ -473,18 +544,15 @@ __device__ __forceinline__ Term step_diffusive_ball(const SegDev<float>& s, uint
     if (p.e >= cap) return Term{HIT_ESCAPED, -1};
     const uint32_t e = p.e + 1;
     p.e = e;
-    const uint4 r = philox4x32_10(make_uint4(pid, e, s.cfgcat, 0u), k0, k1);
-    float dir[3];
-    const float ell = s.vacuum ? m_inf<float>() : diffusive_draw(s, r, dir);
-    // the compensated move, not yet committed (kahan_add split in two)
+    uint32_t k[3];
+    diffusive_codes(diffusive_block(pid, e, s.cfgcat, k0, k1), (e & 1u) != 0, k);
+    float dir[3], v[3];
+    const float ell = s.vacuum ? m_inf<float>() : diffusive_draw(s, k, dir);
+    step_vector(ell, dir, v);
+    // the compensated move, not yet committed
     float y[3], t[3];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        y[i] = ell * dir[i] - p.xc[i];
-        t[i] = p.x[i] + y[i];
-    }
-    const float q0 = t[0] - p.d[0], q1 = t[1] - p.d[1], q2 = t[2] - p.d[2];
-    const bool inside = q0 * q0 + q1 * q1 + q2 * q2 < p.r2;   // false for NaN / infinite steps
+    kahan_try(p.x, p.xc, v, y, t);
+    const bool inside = ball_holds(t, p.d, p.r2);   // false for NaN / infinite steps
     if (!inside) {
         float th, qu = 0.f, qv = 0.f;
         const HitF h = hit_test(s, p.x, dir, ell, th, qu, qv, false);
@@ -495,11 +563,7 @@ __device__ __forceinline__ Term step_diffusive_ball(const SegDev<float>& s, uint
         }
         if (!(ell < m_inf<float>())) return Term{HIT_ESCAPED, -1};
     }
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        p.xc[i] = (t[i] - p.x[i]) - y[i];
-        p.x[i] = t[i];
-    }
+    kahan_commit(p.x, p.xc, y, t);
     ++p.ndiff;
     if (!inside) {
         const float c = clearance(s, p.x) - CLEAR_MARGIN;
@@ -507,6 +571,122 @@ __device__ __forceinline__ Term step_diffusive_ball(const SegDev<float>& s, uint
         p.r2 = c > 0.f ? c * c : -1.f;
     }
     return Term{HIT_NONE, -1};
+}
+
+// The two halves of step_diffusive_ball for a wave that defers its surface tests.
+// diffusive_advance takes the next steps while they stay in the clearance ball: both steps
+// of the current Philox block (one if the next event is odd).  A step that leaves the ball
+// is held (direction in p.d, length in p.r2: the ball is rebuilt after the test anyway) and
+// sets held.  diffusive_resolve finishes a held step exactly as step_diffusive_ball would
+// have.  Steps, events and positions are those of step_diffusive_ball.
+__device__ __forceinline__ void diffusive_substep(const SegDev<float>& s, uint4 w, bool odd, Particle<float>& p,
+                                                  bool& held)
+{
+    uint32_t k[3];
+    diffusive_codes(w, odd, k);
+    p.e += 1;
+    float dir[3], v[3];
+    const float ell = s.vacuum ? m_inf<float>() : diffusive_draw(s, k, dir);
+    step_vector(ell, dir, v);
+    float y[3], t[3];
+    kahan_try(p.x, p.xc, v, y, t);
+    if (ball_holds(t, p.d, p.r2)) {
+        kahan_commit(p.x, p.xc, y, t);
+        ++p.ndiff;
+    } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) p.d[i] = dir[i];
+        p.r2 = ell;
+        held = true;
+    }
+}
+
+__device__ __forceinline__ Term diffusive_advance(const SegDev<float>& s, uint32_t k0, uint32_t k1, uint32_t pid,
+                                                  uint32_t cap, Particle<float>& p, bool& held)
+{
+    if (p.e >= cap) return Term{HIT_ESCAPED, -1};
+    const uint4 w = diffusive_block(pid, p.e + 1, s.cfgcat, k0, k1);
+    if (((p.e + 1) & 1u) == 0) {
+        diffusive_substep(s, w, false, p, held);
+        if (held || p.e >= cap) return Term{HIT_NONE, -1};   // a capped history escapes at its next step
+    }
+    diffusive_substep(s, w, true, p, held);
+    return Term{HIT_NONE, -1};
+}
+
+__device__ __forceinline__ Term diffusive_resolve(const SegDev<float>& s, Particle<float>& p)
+{
+    const float dir[3] = {p.d[0], p.d[1], p.d[2]};
+    const float ell = p.r2;
+    float th, qu = 0.f, qv = 0.f;
+    const HitF h = hit_test(s, p.x, dir, ell, th, qu, qv, false);
+    if (h.state != HIT_NONE) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) kahan_add(p.x[i], p.xc[i], th * dir[i]);
+        return Term{h.state, h.state == HIT_DEPOSITED ? tally_bin(s, qu, qv) : -1};
+    }
+    if (!(ell < m_inf<float>())) return Term{HIT_ESCAPED, -1};
+    float v[3], y[3], t[3];
+    step_vector(ell, dir, v);
+    kahan_try(p.x, p.xc, v, y, t);
+    kahan_commit(p.x, p.xc, y, t);
+    ++p.ndiff;
+    const float c = clearance(s, p.x) - CLEAR_MARGIN;
+    p.d[0] = p.x[0]; p.d[1] = p.x[1]; p.d[2] = p.x[2];
+    p.r2 = c > 0.f ? c * c : -1.f;
+    return Term{HIT_NONE, -1};
+}
+
+// Diffusive steps of the thermalised particle of lane L taken with the whole wave: lane j
+// draws step e + 1 + j (Philox block, direction, length, step vector), then the wave walks
+// the compensated sum through the drawn steps in order on wave-uniform values, stopping
+// before the first step that leaves the clearance ball or passes the event cap.  The sums
+// are those of step_diffusive_ball, operation for operation, so the committed position,
+// event and step counts equal those of taking the same steps one at a time; the step that
+// leaves the ball is left to step_diffusive_ball, which tests it.  Called by the whole
+// wave with L uniform.
+__device__ __forceinline__ void coop_walk(const SegDev<float>& s, uint32_t k0, uint32_t k1, uint32_t cap, uint32_t pid,
+                                          Particle<float>& p, int L, int lane)
+{
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.r2), L));
+    if (!(r2 > 0.f)) return;
+    const uint32_t pidL = (uint32_t)__builtin_amdgcn_readlane((int)pid, L);
+    const uint32_t e0 = (uint32_t)__builtin_amdgcn_readlane((int)p.e, L);
+    float x[3], xc[3], c[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        x[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.x[i]), L));
+        xc[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.xc[i]), L));
+        c[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.d[i]), L));
+    }
+    const uint32_t ej = e0 + 1u + (uint32_t)lane;
+    uint32_t kc[3];
+    diffusive_codes(diffusive_block(pidL, ej, s.cfgcat, k0, k1), (ej & 1u) != 0, kc);
+    float dir[3], v[3];
+    const float ell = s.vacuum ? m_inf<float>() : diffusive_draw(s, kc, dir);
+    step_vector(ell, dir, v);
+    // steps that may be taken at all: within the event cap (the ball test rejects the rest)
+    const uint64_t allowed = __ballot(ej <= cap);
+    int j = 0;
+    for (; j < 64; ++j) {
+        if (!((allowed >> j) & 1ull)) break;
+        float vj[3], y[3], t[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) vj[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), j));
+        kahan_try(x, xc, vj, y, t);
+        if (!__builtin_amdgcn_readfirstlane((int)ball_holds(t, c, r2))) break;
+        kahan_commit(x, xc, y, t);
+    }
+    if (j == 0) return;
+    if (lane == L) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            p.x[i] = x[i];
+            p.xc[i] = xc[i];
+        }
+        p.e = e0 + (uint32_t)j;
+        p.ndiff += (uint32_t)j;
+    }
 }
 
 template <typename R>

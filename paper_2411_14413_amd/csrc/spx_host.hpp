@@ -70,6 +70,8 @@ struct TransportArgs {
 
 constexpr size_t LDS_COUNTERS_MAX = 16384;   // bytes: up to 292 segments
 constexpr uint64_t TICKET_CHUNK = 64;        // tickets a wave claims per global atomic
+constexpr int DEFER_MIN = 8;                  // held diffusive steps that trigger a wave's surface tests
+constexpr int COOP_MAX = 8;                   // drained waves with at most this many live lanes walk cooperatively
 constexpr size_t LDS_TALLY_MAX = 49152;      // bytes: up to 12288 bins
 
 struct GraphKey {

@@ -104,7 +104,40 @@ __device__ __forceinline__ void uniform_loop(const TransportArgs& a, const Block
         const uint64_t M = __ballot(p.st == MODE);
         if (M == 0) break;
         if (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) break;
+        if (drained && __popcll(__ballot(p.st != ST_DEAD)) <= COOP_MAX) break;   // cooperative walks
         if (MODE == ST_BALLISTIC && __popcll(M) < a.ballistic_min && __ballot(p.st == ST_DIFFUSIVE) != 0) break;
+    }
+}
+
+// Diffusive steps of the lanes in segment S with deferred surface tests: a lane whose
+// step leaves its clearance ball holds the step and idles until at least DEFER_MIN lanes
+// hold one (or every diffusive lane does, or the loop is about to end); then the held
+// steps are tested together, so the long test runs in few iterations.  No step is held
+// when the loop returns.
+__device__ __forceinline__ void diffusive_loop(const TransportArgs& a, const BlockTally& bt, const SegDev<float>& S,
+                                               uint32_t pid, Particle<float>& p, LaneAcc& acc, bool drained)
+{
+    bool held = false;
+    for (;;) {
+        if (p.st == ST_DIFFUSIVE && !held) {
+            const Term t = diffusive_advance(S, a.k0, a.k1, pid, a.cap, p, held);
+            if (t.state != HIT_NONE) terminate(a, bt, S, pid, p, t, acc);
+        }
+        const uint64_t H = __ballot(held);
+        const uint64_t M = __ballot(p.st == ST_DIFFUSIVE);
+        bool stop = M == 0 || (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) ||
+                    (drained && __popcll(__ballot(p.st != ST_DEAD)) <= COOP_MAX);
+        if (H != 0 && (stop || H == M || __popcll(H) >= DEFER_MIN)) {
+            if (held) {
+                held = false;
+                const Term t = diffusive_resolve(S, p);
+                if (t.state != HIT_NONE) terminate(a, bt, S, pid, p, t, acc);
+            }
+            stop = __ballot(p.st == ST_DIFFUSIVE) == 0 ||
+                   (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) ||
+                   (drained && __popcll(__ballot(p.st != ST_DEAD)) <= COOP_MAX);
+        }
+        if (stop) break;
     }
 }
 
@@ -184,6 +217,14 @@ k_transport32(TransportArgs a, const SegDev<float>* __restrict__ segs)
             if (drained) break;
             continue;
         }
+        // Last histories of a drained wave: each thermalised lane is walked by the whole
+        // wave (up to 64 steps per pass) before the regular step below.
+        if (drained && __popcll(B | D) <= COOP_MAX) {
+            for (uint64_t W = D; W != 0; W &= W - 1) {
+                const int L = __ffsll((unsigned long long)W) - 1;
+                coop_walk(segs[__builtin_amdgcn_readlane(seg, L)], a.k0, a.k1, a.cap, pid, p, L, lane);
+            }
+        }
         // One kind of event at a time: ballistic flights only once enough lanes are
         // ballistic (or nothing else is left), so that rare ballistic lanes do not drag the
         // long collision path into most iterations of a thermalised wave.
@@ -193,7 +234,7 @@ k_transport32(TransportArgs a, const SegDev<float>* __restrict__ segs)
         if (__ballot(p.st == mode && seg != s0) == 0) {
             const SegDev<float>& S = segs[s0];
             if (mode == ST_BALLISTIC) uniform_loop<ST_BALLISTIC>(a, bt, S, pid, p, acc, drained);
-            else uniform_loop<ST_DIFFUSIVE>(a, bt, S, pid, p, acc, drained);
+            else diffusive_loop(a, bt, S, pid, p, acc, drained);
         } else if (p.st == mode) {
             // lanes of several segments: one flight with per-lane constants
             const SegDev<float>& s = segs[seg];

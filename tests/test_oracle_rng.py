@@ -76,3 +76,45 @@ def test_philox_streams_uniform_and_distinct():
     for c in ([5, 8, 3, 0], [5, 7, 4, 0], [5, 7, 3, 1], [6, 7, 3, 0]):
         assert not np.array_equal(oracle.philox(c, [0, 0])[0], base)
     assert not np.array_equal(oracle.philox([5, 7, 3, 0], [1, 0])[0], base)
+
+
+def _diff_u(n_pairs, seed=77, cfgcat=5):
+    U = np.empty((2 * n_pairs, 3))
+    for i in range(2 * n_pairs):
+        # events 2..2n+1: pairs (2m, 2m+1) share a block; pid varies with the pair
+        U[i] = oracle.diffusive_uniforms(seed, 1000 + i // 64, 2 + i, cfgcat)
+    return U
+
+
+def test_diffusive_uniforms_range_and_lattice():
+    """RN of the diffusive walk lie on the 21-bit lattice (k + 1) 2^-21 of ]0,1]."""
+    U = _diff_u(4096)
+    k = U * 2**21 - 1
+    assert np.all(U > 0) and np.all(U <= 1)
+    assert np.array_equal(k, np.round(k)) and k.min() >= 0 and k.max() < 2**21
+
+
+def test_diffusive_uniforms_uniform_and_independent():
+    """Each RN is uniform (chi-square over 64 cells); the three RN of a step, the two steps
+    sharing a Philox block, and consecutive steps from different blocks are uncorrelated --
+    a shared or overlapping bit field between the halves of a block would show here."""
+    n_pairs = 16384
+    U = _diff_u(n_pairs)
+    n = len(U)
+    for j in range(3):
+        h = np.bincount(np.minimum((U[:, j] * 64).astype(int), 63), minlength=64)
+        chi2 = ((h - n / 64) ** 2 / (n / 64)).sum()
+        assert chi2 < 63 + 5 * np.sqrt(2 * 63), (j, chi2)
+    tol = 5.0 / np.sqrt(n_pairs)
+    even, odd = U[0::2], U[1::2]
+    for a in range(3):
+        for b in range(3):
+            assert abs(np.corrcoef(even[:, a], odd[:, b])[0, 1]) < tol, ("same block", a, b)
+            assert abs(np.corrcoef(odd[:-1, a], even[1:, b])[0, 1]) < tol, ("next block", a, b)
+            if a < b:
+                assert abs(np.corrcoef(U[:, a], U[:, b])[0, 1]) < 5.0 / np.sqrt(n), ("same step", a, b)
+    # low bits too: the parity of the 21-bit code is a fair coin in both halves
+    k = np.round(U * 2**21 - 1).astype(np.int64)
+    for half in (k[0::2], k[1::2]):
+        for j in range(3):
+            assert abs((half[:, j] & 1).mean() - 0.5) < 5 * 0.5 / np.sqrt(len(half))
