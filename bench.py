@@ -52,10 +52,11 @@ OPS = dict(
     BALLISTIC=PHILOX + 3 * U01 + 60 + 6 + 100 + 15 + 2,
     # gas-velocity block and 4 uniforms, Box-Muller 40, kinematics with the table lookup 130
     COLLIDE=PHILOX + 4 * U01 + 40 + 130,
-    # block, 3 uniforms, isotropic direction and exponential length 24, step vector 3,
-    # compensated move 12, clearance-ball test 7, bookkeeping 2, plus 2 for the ~1.3 % of steps
-    # that leave the ball and take the surface test and a new clearance (~150 slots)
-    DIFFUSIVE=PHILOX + 3 * U01 + 24 + 3 + 12 + 7 + 2 + 2,
+    # half a block (two steps per block), 21-bit codes 5 and their 3 RN 6, isotropic direction
+    # and exponential length 24, step vector 3, compensated move 12, clearance-ball test 7,
+    # bookkeeping 2, plus 2 for the ~1.3 % of steps that leave the ball and take the surface
+    # test and a new clearance (~150 slots)
+    DIFFUSIVE=PHILOX // 2 + 5 + 6 + 24 + 3 + 12 + 7 + 2 + 2,
 )
 # Peak: the FP32 vector rate of the MI355X, 157.3 TFLOP/s = 78.6e12 FMA/s, i.e. 128 lanes per
 # CU per clock (256 CUs, 2.4 GHz); one slot = one full-rate 32-bit lane operation.

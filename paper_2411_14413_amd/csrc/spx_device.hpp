@@ -461,7 +461,7 @@ __device__ __forceinline__ Term step_mode(const SegDev<R>& s, const TabDev<R>& t
     } else {
         uint32_t k[3];
         diffusive_codes(diffusive_block(pid, e, s.cfgcat, k0, k1), (e & 1u) != 0, k);
-        ell = s.vacuum ? m_inf<R>() : diffusive_draw(s, k, p.d);
+        ell = diffusive_draw(s, k, p.d);   // diffusive only after a gas collision: never in vacuum
     }
     R t, qu = (R)0, qv = (R)0;
     const HitF h = hit_test(s, p.x, p.d, ell, t, qu, qv, e == 1u);
@@ -547,7 +547,7 @@ __device__ __forceinline__ Term step_diffusive_ball(const SegDev<float>& s, uint
     uint32_t k[3];
     diffusive_codes(diffusive_block(pid, e, s.cfgcat, k0, k1), (e & 1u) != 0, k);
     float dir[3], v[3];
-    const float ell = s.vacuum ? m_inf<float>() : diffusive_draw(s, k, dir);
+    const float ell = diffusive_draw(s, k, dir);   // diffusive only after a gas collision
     step_vector(ell, dir, v);
     // the compensated move, not yet committed
     float y[3], t[3];
@@ -586,7 +586,7 @@ __device__ __forceinline__ void diffusive_substep(const SegDev<float>& s, uint4 
     diffusive_codes(w, odd, k);
     p.e += 1;
     float dir[3], v[3];
-    const float ell = s.vacuum ? m_inf<float>() : diffusive_draw(s, k, dir);
+    const float ell = diffusive_draw(s, k, dir);   // diffusive only after a gas collision
     step_vector(ell, dir, v);
     float y[3], t[3];
     kahan_try(p.x, p.xc, v, y, t);
@@ -663,7 +663,7 @@ __device__ __forceinline__ void coop_walk(const SegDev<float>& s, uint32_t k0, u
     uint32_t kc[3];
     diffusive_codes(diffusive_block(pidL, ej, s.cfgcat, k0, k1), (ej & 1u) != 0, kc);
     float dir[3], v[3];
-    const float ell = s.vacuum ? m_inf<float>() : diffusive_draw(s, kc, dir);
+    const float ell = diffusive_draw(s, kc, dir);
     step_vector(ell, dir, v);
     // steps that may be taken at all: within the event cap (the ball test rejects the rest)
     const uint64_t allowed = __ballot(ej <= cap);
