@@ -61,18 +61,22 @@ OPS = dict(
 # Peak: the FP32 vector rate of the MI355X, 157.3 TFLOP/s = 78.6e12 FMA/s, i.e. 128 lanes per
 # CU per clock (256 CUs, 2.4 GHz); one slot = one full-rate 32-bit lane operation.
 PEAK_ALU = 256 * 128 * 2.4e9
+# HBM bytes per launch of each kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch, scaled by a copy probe) on the default workload; None until taken for the current
+# kernels.
+TRAFFIC = {}
 
 
 def algorithmic_ops(counters):
-    """ALU slots of one run from its counters [n_seg, 7]."""
+    """ALU slots of one run from its counters [n_seg, 7]: (ballistic phase, diffusive phase)."""
     N = counters[:, 0].sum()
     coll = counters[:, 4].sum()
     diff = counters[:, 5].sum()
     therm = counters[:, 6].sum()
     ballistic_flights = coll + (N - therm)     # every collision, plus the last flight of atoms never thermalised
     diffusive_steps = diff + therm             # every diffusive step, plus the last step of thermalised atoms
-    return float(N * OPS["LAUNCH"] + ballistic_flights * OPS["BALLISTIC"] + coll * OPS["COLLIDE"] +
-                 diffusive_steps * OPS["DIFFUSIVE"])
+    return (float(N * OPS["LAUNCH"] + ballistic_flights * OPS["BALLISTIC"] + coll * OPS["COLLIDE"]),
+            float(diffusive_steps * OPS["DIFFUSIVE"]))
 
 
 def workload(name, scale=1.0):
@@ -101,23 +105,28 @@ def tally_error(counts_seg):
     return vals
 
 
-def time_steps(plan, bufs, seed, steps, warmup):
+def time_steps(plan, bufs, seed, steps, warmup, phase_times=True):
     import torch
     for _ in range(warmup):
         plan.run_into(seed, bufs)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    phases = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for a, b in ev:
         a.record(stream)
         plan.run_into(seed, bufs)
         b.record(stream)
+        # per-kernel device times of this step, from the HIP events the plan records between
+        # its kernels on this stream (waits for the step: a few microseconds per step)
+        if phase_times:
+            phases.append(plan.phase_times())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = [a.elapsed_time(b) for a, b in ev]
-    return wall, ms
+    return wall, ms, phases
 
 
 def cpu_baseline(cfgs, params, target_s):
@@ -149,7 +158,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=25.0,
                     help="target of the CPU pilot-based sizing (the measured run usually takes about half)")
-    ap.add_argument("--launch", default="", help="blocks,threads,refill_min,ballistic_min instead of autotuning")
+    ap.add_argument("--launch", default="", help="blocks,threads,refill_min,refill_ballistic instead of autotuning")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -187,7 +196,7 @@ def main():
         launch = plan.launch if args.no_autotune else plan.autotune()
     tune_s = time.perf_counter() - t
     bufs = plan.allocate(profiles=True)
-    wall, ms = time_steps(plan, bufs, args.seed, args.steps, args.warmup)
+    wall, ms, phases = time_steps(plan, bufs, args.seed, args.steps, args.warmup)
     counters = bufs["counters"].view(plan.n_segments, spx._native.N_COUNTERS).cpu().numpy().astype(np.float64)
     n_part = float(counters[:, 0].sum())
     assert n_part == plan.n_particles
@@ -200,14 +209,21 @@ def main():
     counts32 = [bufs["counts"][o:o + nv * nu].cpu().numpy() for o, (nv, nu) in zip(plan.bin_off, plan.shapes)]
     eps32 = tally_error(counts32)
 
-    ops = algorithmic_ops(counters)
-    achieved = ops / (ms_med * 1e-3)
-    roofline = dict(bound="alu", kernel="k_transport32", achieved=achieved / 1e12, peak=PEAK_ALU / 1e12,
-                    unit="TOP/s", frac=achieved / PEAK_ALU, traffic=None,
-                    ops_per_launch=ops, launch_ms=ms_med,
-                    note="VALU issue slots per lane counted from the algorithm (quarter-rate ops = 4 slots); "
-                         "peak = 256 CU x 128 lanes x 2.4 GHz (the FP32 vector rate); launch time = HIP-event time "
-                         "of the graph replay (zero + transport + normalise)")
+    ops_b, ops_d = algorithmic_ops(counters)
+    ms_b = float(np.mean([p[0] for p in phases]))
+    ms_d = float(np.mean([p[1] for p in phases]))
+    kern = {"k_ballistic32": (ops_b, ms_b), "k_diffusive32": (ops_d, ms_d)}
+    dominant = max(kern, key=lambda k: kern[k][1])
+    ops, ms_k = kern[dominant]
+    achieved = ops / (ms_k * 1e-3)
+    roofline = dict(bound="alu", kernel=dominant, achieved=achieved / 1e12, peak=PEAK_ALU / 1e12,
+                    unit="TOP/s", frac=achieved / PEAK_ALU, traffic=TRAFFIC.get(dominant),
+                    ops_per_launch=ops, launch_ms=ms_k,
+                    phases={k: dict(ops=o, ms=t, achieved=o / (t * 1e-3) / 1e12 if t > 0 else None,
+                                    frac=o / (t * 1e-3) / PEAK_ALU if t > 0 else None) for k, (o, t) in kern.items()},
+                    note="VALU issue slots per lane counted from the algorithm (a 32x32->64 multiply or a native "
+                         "transcendental = 4 slots); peak = 256 CU x 128 lanes x 2.4 GHz (the FP32 vector rate); "
+                         "kernel time = mean over the timed steps of HIP events recorded between the kernels")
 
     result = {
         "metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
@@ -226,7 +242,7 @@ def main():
     if not args.no_fp64:
         plan64 = spx.Plan(cfgs, params, precision=64)
         bufs64 = plan64.allocate(profiles=True)
-        wall64, ms64 = time_steps(plan64, bufs64, args.seed, 2, 1)
+        wall64, ms64, _ = time_steps(plan64, bufs64, args.seed, 2, 1, phase_times=False)
         c64 = bufs64["counters"].view(plan.n_segments, spx._native.N_COUNTERS).cpu().numpy().astype(np.float64)
         counts64 = [bufs64["counts"][o:o + nv * nu].cpu().numpy() for o, (nv, nu) in zip(plan64.bin_off, plan64.shapes)]
         eps64 = tally_error(counts64)

@@ -160,19 +160,24 @@ int spx_plan_layout(const spx_plan* plan, uint64_t* h_bin_off, uint64_t* h_first
 int spx_run(spx_plan* plan, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters,
             double* d_profiles, spx_record* d_records, void* stream);
 
-/* Choose launch parameters of the FP32 transport (block size, refill and ballistic
+/* Choose launch parameters of the FP32 transport (block size and the two refill
  * thresholds) by timing short runs on `stream`; synchronous; results are unaffected. */
 int spx_autotune(spx_plan* plan, void* stream);
 
-/* Current FP32-transport launch parameters: blocks, threads per block, refill threshold
- * (a wave refills its dead lanes once at least this many are dead) and ballistic threshold
- * (a wave runs ballistic flights once at least this many lanes are ballistic, else
- * diffusive steps).  Any pointer may be NULL. */
+/* Current FP32-transport launch parameters, shared by its two persistent kernels (the
+ * ballistic phase, launch to thermalisation, and the diffusive phase): blocks, threads per
+ * block, the diffusive phase's refill threshold (a wave refills its dead lanes once at least
+ * this many are dead) and the ballistic phase's.  Any pointer may be NULL. */
 int spx_get_launch(const spx_plan* plan, int32_t* blocks, int32_t* threads, int32_t* refill_min,
-                   int32_t* ballistic_min);
+                   int32_t* refill_ballistic);
 /* Override them: threads a multiple of 64 in [64, 1024], thresholds in [1, 64]; blocks <= 0
  * (or above the resident limit) fills the device at the occupancy limit. */
-int spx_set_launch(spx_plan* plan, int32_t blocks, int32_t threads, int32_t refill_min, int32_t ballistic_min);
+int spx_set_launch(spx_plan* plan, int32_t blocks, int32_t threads, int32_t refill_min, int32_t refill_ballistic);
+
+/* Device time [ms] of the two phases of the last FP32 spx_run of this plan, summed over its
+ * rounds (HIP events recorded between the kernels; waits for that run to finish).
+ * SPX_ESTATE before the first FP32 run. */
+int spx_phase_times(spx_plan* plan, float* ms_ballistic, float* ms_diffusive);
 
 /* Copy the FP64 scattering table to the host: h_theta[ne * ns] (row i = log10 eps node),
  * h_betamax[ne]. */

@@ -161,12 +161,18 @@ class Plan:
         b, t, r, m = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         check(lib().spx_get_launch(self._h, ctypes.byref(b), ctypes.byref(t), ctypes.byref(r), ctypes.byref(m)),
               "spx_get_launch")
-        return dict(blocks=b.value, threads=t.value, refill_min=r.value, ballistic_min=m.value)
+        return dict(blocks=b.value, threads=t.value, refill_min=r.value, refill_ballistic=m.value)
 
-    def set_launch(self, blocks: int = 0, threads: int = 256, refill_min: int = 8, ballistic_min: int = 8):
-        check(lib().spx_set_launch(self._h, int(blocks), int(threads), int(refill_min), int(ballistic_min)),
+    def set_launch(self, blocks: int = 0, threads: int = 256, refill_min: int = 8, refill_ballistic: int = 8):
+        check(lib().spx_set_launch(self._h, int(blocks), int(threads), int(refill_min), int(refill_ballistic)),
               "spx_set_launch")
         return self.launch
+
+    def phase_times(self):
+        """(ballistic ms, diffusive ms) of the last FP32 run (waits for it)."""
+        b, d = ctypes.c_float(), ctypes.c_float()
+        check(lib().spx_phase_times(self._h, ctypes.byref(b), ctypes.byref(d)), "spx_phase_times")
+        return b.value, d.value
 
     # -- introspection ---------------------------------------------------------------------
     def table(self):

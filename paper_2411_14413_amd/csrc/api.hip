@@ -282,10 +282,11 @@ static void release(Plan* P)
     if (!P) return;
     if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
-    void* ptrs[] = {P->d_theta64, P->d_betamax64, P->d_theta32, P->d_betamax32, P->d_seg32, P->d_seg64,
-                    P->d_tfirst,  P->d_torder,    P->d_ticket,  P->d_bin_off,   P->d_seg_norm};
+    void* ptrs[] = {P->d_theta64, P->d_betamax64, P->d_theta32, P->d_betamax32, P->d_seg32,   P->d_seg64,
+                    P->d_tfirst,  P->d_torder,    P->d_qstate,  P->d_queue,     P->d_bin_off, P->d_seg_norm};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
+    for (hipEvent_t e : P->phase_events) (void)hipEventDestroy(e);
     if (P->work_stream) (void)hipStreamDestroy(P->work_stream);
     delete P;
 }
@@ -339,7 +340,7 @@ static int create(const spx_config* cfgs, int n_cfgs, const spx_params* prm, Pla
     chk(dalloc(&P->d_theta64, (size_t)ne * ns)) && chk(dalloc(&P->d_betamax64, ne)) &&
         chk(dalloc(&P->d_theta32, (size_t)ne * ns)) && chk(dalloc(&P->d_betamax32, ne)) &&
         chk(dalloc(&P->d_seg32, n)) && chk(dalloc(&P->d_seg64, n)) && chk(dalloc(&P->d_tfirst, n + 1)) &&
-        chk(dalloc(&P->d_torder, n)) && chk(dalloc(&P->d_ticket, 1)) && chk(dalloc(&P->d_bin_off, n + 1)) &&
+        chk(dalloc(&P->d_torder, n)) && chk(dalloc(&P->d_qstate, 3)) && chk(dalloc(&P->d_bin_off, n + 1)) &&
         chk(dalloc(&P->d_seg_norm, n));
     if (rc == SPX_OK) rc = build_tables(P);
     if (rc != SPX_OK) {
@@ -371,6 +372,19 @@ static int create(const spx_config* cfgs, int n_cfgs, const spx_params* prm, Pla
     std::vector<uint64_t> tfirst(n + 1, 0);
     for (int o = 0; o < n; ++o) tfirst[o + 1] = tfirst[o] + P->seg[order[o]].N;
     P->n_tickets = tfirst[n];
+    if (prm->precision == 32) {
+        // thermalisation queue of one round of the batched path (48 B per ticket of a round)
+        // thermalised atoms of a round, plus the slots a resident wave may leave unused
+        const uint64_t r = rounds_of(P->n_tickets);
+        const uint64_t waves = std::max<uint64_t>(QUEUE_SLACK_WAVES, (uint64_t)P->n_cu * 32);
+        P->queue_cap = (r ? (P->n_tickets + r - 1) / r : 0) + waves * QUEUE_CHUNK;
+        if (dalloc(&P->d_queue, P->queue_cap) != SPX_OK) {
+            set_error("hipMalloc of the thermalisation queue (" + std::to_string(P->queue_cap * sizeof(ThermRec)) +
+                      " bytes) failed");
+            release(P);
+            return SPX_ENOMEM;
+        }
+    }
     std::vector<uint64_t> bo(P->h_bin_off);
     bo.push_back(P->n_bins_total);
     hipStream_t st = P->work_stream;
@@ -398,6 +412,54 @@ static int create(const spx_config* cfgs, int n_cfgs, const spx_params* prm, Pla
     return SPX_OK;
 }
 
+// Timing events of the batched path, added to its captured graph (a linear chain of kernel
+// nodes): per round, one event recorded before the ballistic kernel, one between the two
+// kernels and one after the diffusive kernel (spx_phase_times).
+static int add_phase_events(Plan* P, hipGraph_t g)
+{
+    const size_t n_rounds = (size_t)rounds_of(P->n_tickets);
+    while (P->phase_events.size() < 3 * n_rounds) {
+        hipEvent_t e = nullptr;
+        SPX_HIP(hipEventCreate(&e));
+        P->phase_events.push_back(e);
+    }
+    std::vector<hipGraphNode_t> chain;
+    hipGraphNode_t node = nullptr;
+    size_t n = 1;
+    SPX_HIP(hipGraphGetRootNodes(g, &node, &n));
+    while (n == 1) {
+        chain.push_back(node);
+        size_t nd = 0;
+        SPX_HIP(hipGraphNodeGetDependentNodes(node, nullptr, &nd));
+        if (nd > 1) break;
+        if (nd == 1) SPX_HIP(hipGraphNodeGetDependentNodes(node, &node, &nd));
+        n = nd;
+    }
+    size_t r = 0;
+    for (size_t i = 0; i + 1 < chain.size() && r < n_rounds; ++i) {
+        hipGraphNodeType ty;
+        SPX_HIP(hipGraphNodeGetType(chain[i], &ty));
+        if (ty != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp{};
+        SPX_HIP(hipGraphKernelNodeGetParams(chain[i], &kp));
+        if (kp.func != ballistic_kernel() || i == 0) continue;
+        const hipGraphNode_t prev = chain[i - 1], bal = chain[i], dif = chain[i + 1];
+        hipGraphNode_t e0, e1, e2;
+        SPX_HIP(hipGraphAddEventRecordNode(&e0, g, &prev, 1, P->phase_events[3 * r]));
+        SPX_HIP(hipGraphAddDependencies(g, &e0, &bal, 1));
+        SPX_HIP(hipGraphAddEventRecordNode(&e1, g, &bal, 1, P->phase_events[3 * r + 1]));
+        SPX_HIP(hipGraphAddDependencies(g, &e1, &dif, 1));
+        SPX_HIP(hipGraphAddEventRecordNode(&e2, g, &dif, 1, P->phase_events[3 * r + 2]));
+        if (i + 2 < chain.size()) SPX_HIP(hipGraphAddDependencies(g, &e2, &chain[i + 2], 1));
+        ++r;
+    }
+    if (r != n_rounds) {
+        set_error("internal: unexpected shape of the transport graph");
+        return SPX_ESTATE;
+    }
+    return SPX_OK;
+}
+
 static int run(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
                spx_record* d_records, hipStream_t st)
 {
@@ -412,7 +474,7 @@ static int run(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters,
     key.blocks = P->blocks;
     key.threads = P->threads;
     key.refill = P->refill_min;
-    key.bmin = P->ballistic_min;
+    key.refill_b = P->refill_ballistic;
     if (!P->graph_exec || !(key == P->graph_key)) {
         if (P->graph_exec) {
             SPX_HIP(hipGraphExecDestroy(P->graph_exec));
@@ -425,7 +487,7 @@ static int run(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters,
         SPX_HIP(hipStreamBeginCapture(P->work_stream, hipStreamCaptureModeThreadLocal));
         const int rc = launch_transport32(P, seed, d_counts, d_counters, d_profiles, d_records, P->work_stream,
                                           P->d_tfirst, P->n_tickets, P->blocks, P->threads, P->refill_min,
-                                          P->ballistic_min);
+                                          P->refill_ballistic, nullptr);
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(P->work_stream, &g);
         if (rc != SPX_OK) {
@@ -433,6 +495,11 @@ static int run(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters,
             return rc;
         }
         SPX_HIP(ec);
+        const int rt = add_phase_events(P, g);
+        if (rt != SPX_OK) {
+            (void)hipGraphDestroy(g);
+            return rt;
+        }
         P->graph = g;
         SPX_HIP(hipGraphInstantiate(&P->graph_exec, P->graph, nullptr, nullptr, 0));
         P->graph_key = key;
@@ -472,7 +539,7 @@ static int autotune(Plan* P, hipStream_t st)
     if (rc == SPX_OK && hipMemcpyAsync(d_tf, tf.data(), sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess)
         rc = SPX_EDEVICE;
     float best = 1e30f;
-    int bb = P->blocks, bt = P->threads, br = P->refill_min, bm = P->ballistic_min;
+    int bb = P->blocks, bt = P->threads, br = P->refill_min, bm = P->refill_ballistic;
     const int thread_opts[] = {256, 512, 1024};
     const int mode_opts[][2] = {{4, 4}, {8, 8}, {16, 16}};
     for (int t : thread_opts) {
@@ -485,7 +552,7 @@ static int autotune(Plan* P, hipStream_t st)
             for (int rep = 0; rep < 2 && rc == SPX_OK; ++rep) {
                 if (hipEventRecord(e0, st) != hipSuccess) rc = SPX_EDEVICE;
                 if (rc == SPX_OK) rc = launch_transport32(P, 0x5eed, d_counts, d_ctr, nullptr, nullptr, st, d_tf, tf[n],
-                                                          blocks, t, ro[0], ro[1]);
+                                                          blocks, t, ro[0], ro[1], nullptr);
                 if (rc == SPX_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
                     rc = SPX_EDEVICE;
                 float ms = 0.f;
@@ -512,7 +579,7 @@ static int autotune(Plan* P, hipStream_t st)
     P->blocks = bb;
     P->threads = bt;
     P->refill_min = br;
-    P->ballistic_min = bm;
+    P->refill_ballistic = bm;
     return SPX_OK;
 }
 
@@ -588,22 +655,22 @@ int spx_autotune(spx_plan* P, void* stream)
 }
 
 int spx_get_launch(const spx_plan* P, int32_t* blocks, int32_t* threads, int32_t* refill_min,
-                   int32_t* ballistic_min)
+                   int32_t* refill_ballistic)
 {
     if (!P) return fail("null plan");
     if (blocks) *blocks = P->blocks;
     if (threads) *threads = P->threads;
     if (refill_min) *refill_min = P->refill_min;
-    if (ballistic_min) *ballistic_min = P->ballistic_min;
+    if (refill_ballistic) *refill_ballistic = P->refill_ballistic;
     return SPX_OK;
 }
 
-int spx_set_launch(spx_plan* P, int32_t blocks, int32_t threads, int32_t refill_min, int32_t ballistic_min)
+int spx_set_launch(spx_plan* P, int32_t blocks, int32_t threads, int32_t refill_min, int32_t refill_ballistic)
 {
     if (!P) return fail("null plan");
     if (threads < 64 || threads > 1024 || (threads & 63)) return fail("threads must be a multiple of 64 in [64, 1024]");
     if (refill_min < 1 || refill_min > 64) return fail("refill_min must be in [1, 64]");
-    if (ballistic_min < 1 || ballistic_min > 64) return fail("ballistic_min must be in [1, 64]");
+    if (refill_ballistic < 1 || refill_ballistic > 64) return fail("refill_ballistic must be in [1, 64]");
     int bpc = 0;
     SPX_TRY(occupancy_transport32(P, threads, &bpc));
     if (bpc < 1) return fail("transport kernel does not fit with this block size");
@@ -612,7 +679,7 @@ int spx_set_launch(spx_plan* P, int32_t blocks, int32_t threads, int32_t refill_
     P->blocks = (blocks <= 0 || blocks > limit) ? limit : blocks;
     P->threads = threads;
     P->refill_min = refill_min;
-    P->ballistic_min = ballistic_min;
+    P->refill_ballistic = refill_ballistic;
     return SPX_OK;
 }
 
@@ -672,6 +739,29 @@ int spx_area_centres(int32_t n_areas, double pitch, double* h_out)
         h_out[2 * k] = pitch * pts[k].i;
         h_out[2 * k + 1] = pitch * pts[k].j;
     }
+    return SPX_OK;
+}
+
+int spx_phase_times(spx_plan* P, float* ms_ballistic, float* ms_diffusive)
+{
+    if (!P || !ms_ballistic || !ms_diffusive) return fail("null argument");
+    if (P->params.precision != 32 || !P->graph_exec) {
+        set_error("no batched FP32 run of this plan yet");
+        return SPX_ESTATE;
+    }
+    SPX_HIP(hipSetDevice(P->device));
+    const size_t n_ev = 3 * (size_t)rounds_of(P->n_tickets);
+    float b = 0.f, d = 0.f;
+    for (size_t r = 0; r + 2 < n_ev; r += 3) {
+        SPX_HIP(hipEventSynchronize(P->phase_events[r + 2]));
+        float t1 = 0.f, t2 = 0.f;
+        SPX_HIP(hipEventElapsedTime(&t1, P->phase_events[r], P->phase_events[r + 1]));
+        SPX_HIP(hipEventElapsedTime(&t2, P->phase_events[r + 1], P->phase_events[r + 2]));
+        b += t1;
+        d += t2;
+    }
+    *ms_ballistic = b;
+    *ms_diffusive = d;
     return SPX_OK;
 }
 

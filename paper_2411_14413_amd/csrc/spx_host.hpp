@@ -47,27 +47,45 @@ struct SegHost {
     double cost;          // relative expected work per particle (ticket ordering)
 };
 
-// Launch arguments of the batched FP32 transport kernel.
+// A thermalised atom handed from the ballistic to the diffusive phase (48 B).
+struct alignas(16) ThermRec {
+    float x[3], xc[3];          // compensated position (chamber frame)
+    float E;                    // energy at thermalisation (reported in the record)
+    uint32_t pid;               // particle index within its segment
+    uint32_t seg;               // segment
+    uint32_t e;                 // events taken so far
+    uint32_t pad[2];
+};
+static_assert(sizeof(ThermRec) == 48, "ThermRec layout");
+
+// Launch arguments of the two batched FP32 transport kernels (one round = one chunk of the
+// ticket space: the ballistic phase of every ticket, then the diffusive phase of the atoms
+// it thermalised).
 struct TransportArgs {
     const SegDev<float>* segs;
     TabDev<float> tab;
     const uint64_t* tfirst;     // [n_seg + 1] first ticket of each position in ticket order
     const uint32_t* torder;     // [n_seg] segment at each position
-    uint64_t* ticket;           // global ticket counter
+    ThermRec* queue;            // thermalised atoms of the round (capacity >= tickets of a round)
+    uint64_t* qstate;           // [0] ballistic ticket counter, [1] queue length, [2] diffusive ticket counter
     unsigned long long* counts;
     unsigned long long* counters;
     spx_record* records;
-    uint64_t total;             // tickets
+    uint64_t tbase;             // first ticket of the round
+    uint64_t total;             // tickets of the round
     uint32_t k0, k1;            // Philox key (seed words)
     uint32_t cap;
     int32_t n_seg;
-    int32_t refill_min;         // refill a wave's dead lanes once at least this many
-    int32_t ballistic_min;      // run ballistic flights once at least this many lanes are ballistic
+    int32_t refill_min;         // diffusive phase: refill a wave's dead lanes once at least this many
+    int32_t refill_ballistic;   // ballistic phase: the same threshold
     uint32_t n_bins;            // tally bins of the plan
     int32_t lds_counters;       // per-segment counters privatised in LDS
     int32_t lds_tally;          // whole tally privatised in LDS (u32 per bin)
 };
 
+constexpr uint64_t ROUND_MAX = 1ull << 25;   // tickets per round: a 1.6 GB queue of thermalised atoms
+constexpr uint64_t QUEUE_CHUNK = 64;         // queue slots a wave reserves per atomic
+constexpr uint64_t QUEUE_SLACK_WAVES = 8192;  // waves that may leave slots unused (32 per CU, 256 CUs)
 constexpr size_t LDS_COUNTERS_MAX = 16384;   // bytes: up to 292 segments
 constexpr uint64_t TICKET_CHUNK = 64;        // tickets a wave claims per global atomic
 constexpr int DEFER_MIN = 8;                  // held diffusive steps that trigger a wave's surface tests
@@ -80,12 +98,12 @@ struct GraphKey {
     void* counters = nullptr;
     void* profiles = nullptr;
     void* records = nullptr;
-    int blocks = 0, threads = 0, refill = 0, bmin = 0;
+    int blocks = 0, threads = 0, refill = 0, refill_b = 0;
     bool operator==(const GraphKey& o) const
     {
         return seed == o.seed && counts == o.counts && counters == o.counters && profiles == o.profiles &&
                records == o.records && blocks == o.blocks && threads == o.threads && refill == o.refill &&
-               bmin == o.bmin;
+               refill_b == o.refill_b;
     }
 };
 
@@ -110,12 +128,15 @@ struct spx_plan {
     spx::SegDev<double>* d_seg64 = nullptr;
     uint64_t* d_tfirst = nullptr;
     uint32_t* d_torder = nullptr;
-    uint64_t* d_ticket = nullptr;
+    spx::ThermRec* d_queue = nullptr;       // thermalised atoms of a round (FP32 plans)
+    uint64_t queue_cap = 0;
+    uint64_t* d_qstate = nullptr;           // ticket counters and queue length
+    std::vector<hipEvent_t> phase_events;   // recorded in the graph: round start, ballistic end, diffusive end
     uint64_t* d_bin_off = nullptr;          // [n_seg + 1]
     double* d_seg_norm = nullptr;           // [n_seg]
     uint64_t n_tickets = 0;
 
-    int blocks = 0, threads = 256, refill_min = 8, ballistic_min = 8;
+    int blocks = 0, threads = 256, refill_min = 8, refill_ballistic = 8;
     int max_blocks_per_cu = 0, n_cu = 0;
 
     hipGraph_t graph = nullptr;
@@ -126,10 +147,15 @@ struct spx_plan {
 namespace spx {
 using Plan = spx_plan;
 int build_tables(Plan* P);
+// events (nullable, not while capturing): 3 per round, recorded at the round's start, after
+// its ballistic phase and after its diffusive phase.
 int launch_transport32(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
                        spx_record* d_records, hipStream_t st, const uint64_t* tfirst, uint64_t total,
-                       int blocks, int threads, int refill_min, int ballistic_min);
+                       int blocks, int threads, int refill_min, int refill_ballistic, const hipEvent_t* events);
+uint64_t rounds_of(uint64_t total);
+const void* ballistic_kernel();
+const void* diffusive_kernel();
 int launch_transport64(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
                        spx_record* d_records, hipStream_t st);
-int occupancy_transport32(const Plan* P, int threads, int* blocks_per_cu);
+int occupancy_transport32(const Plan* P, int threads, int* blocks_per_cu);   // the smaller of the two kernels
 }  // namespace spx

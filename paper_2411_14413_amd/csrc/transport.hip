@@ -1,15 +1,18 @@
 // transport.hip -- the two transport paths and their tally kernels.
 //
-// Batched FP32 path (k_transport32): one persistent launch covers every
-// (configuration, cathode) segment of a plan.  Each lane holds one particle in
-// registers; when lanes die the wave claims a run of tickets with a single atomic
-// (ballot + mbcnt prefix gives each dead lane its ticket), maps each ticket to
-// (segment, particle) through the prefix table, and launches the new particles.
-// Every iteration advances each live lane by one flight.  Because the random
-// numbers are keyed by (seed, segment, particle, event), the result does not depend
-// on which lane or wave ran a particle, nor on the ticket order.  Deposits go to
-// the integer tally with 64-bit atomics; per-segment counters are accumulated in
-// registers while a lane stays in one segment and flushed when it changes.
+// Batched FP32 path: every (configuration, cathode) segment of a plan runs in rounds of
+// at most ROUND_MAX tickets, each round as two persistent launches.  k_ballistic32 takes
+// every ticket of the round from its launch through its ballistic flights and collisions;
+// an atom that ends on a surface (or escapes) is finished there, an atom that thermalises
+// is handed over to a queue in HBM (48 B).  k_diffusive32 then runs the diffusive walks of
+// the queued atoms.  Each lane holds one atom in registers; when lanes die, the wave claims
+// a run of tickets with a single atomic (ballot + mbcnt prefix gives each dead lane its
+// ticket).  Splitting the history at thermalisation keeps every lane of a wave in the same
+// kind of event: new atoms (ballistic) and walkers (diffusive) never share a wave.  The
+// random numbers are keyed by (seed, segment, particle, event), so the result does not
+// depend on which lane, wave or launch ran an atom, nor on the queue order.  Deposits go
+// to a per-block LDS tally (or 64-bit global atomics when it does not fit); per-segment
+// counters are accumulated in registers while a lane stays in one segment.
 //
 // Plain FP64 path (k_transport64): one thread per particle runs the whole history;
 // one launch per segment.  It is the comparator for the batched path.
@@ -88,24 +91,129 @@ __device__ __forceinline__ void terminate(const TransportArgs& a, const BlockTal
     p.st = ST_DEAD;
 }
 
-// Flights of the lanes in state MODE while the wave's situation allows: every such lane
-// in segment S (uniform, so its constants stay in scalar registers across the loop).
-// Leaves when the wave should refill, switch event kind, or has nothing left in MODE.
-template <int MODE>
-__device__ __forceinline__ void uniform_loop(const TransportArgs& a, const BlockTally& bt, const SegDev<float>& S,
-                                             uint32_t pid, Particle<float>& p, LaneAcc& acc, bool drained)
+// Wave-private run of tickets [tk, tk_end), claimed TICKET_CHUNK at a time from a global
+// counter with one atomic, so that refills rarely touch the counter.
+struct Tickets {
+    uint64_t tk = 0, tk_end = 0;
+    bool drained = false;     // wave-uniform: the ticket space is exhausted
+};
+
+// Tickets for the dead lanes `dead` of the wave: consecutive tickets of the wave's run in lane
+// order.  Returns this lane's ticket, or ~0 when it gets none.
+__device__ __forceinline__ uint64_t claim(Tickets& T, uint64_t* counter, uint64_t total, uint64_t dead, int lane,
+                                          uint64_t lt_mask)
+{
+    if (T.tk == T.tk_end) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd((unsigned long long*)counter, (unsigned long long)TICKET_CHUNK);
+        base = __shfl(base, 0);
+        if (base >= total) {
+            T.drained = true;
+            return ~0ull;
+        }
+        T.tk = base;
+        T.tk_end = (base + TICKET_CHUNK < total) ? base + TICKET_CHUNK : total;
+    }
+    const uint64_t n_dead = (uint64_t)__popcll(dead);
+    const uint64_t avail = T.tk_end - T.tk;
+    const uint64_t take = avail < n_dead ? avail : n_dead;
+    const uint64_t base = T.tk;
+    T.tk += take;
+    const uint64_t rank = (uint64_t)__popcll(dead & lt_mask);
+    return (((dead >> lane) & 1ull) && rank < take) ? base + rank : ~0ull;
+}
+
+__device__ __forceinline__ void lds_setup(const TransportArgs& a, BlockTally& bt, unsigned long long* lds)
+{
+    bt.lcnt = lds;
+    bt.ltally = (uint32_t*)(lds + (a.lds_counters ? (size_t)a.n_seg * N_COUNTERS : 0));
+    if (a.lds_counters)
+        for (int i = threadIdx.x; i < a.n_seg * N_COUNTERS; i += blockDim.x) bt.lcnt[i] = 0;
+    if (a.lds_tally)
+        for (uint32_t i = threadIdx.x; i < a.n_bins; i += blockDim.x) bt.ltally[i] = 0;
+    __syncthreads();
+}
+
+__device__ __forceinline__ void lds_flush(const TransportArgs& a, const BlockTally& bt, LaneAcc& acc)
+{
+    flush_acc(a, bt, acc);
+    __syncthreads();
+    if (a.lds_counters)
+        for (int i = threadIdx.x; i < a.n_seg * N_COUNTERS; i += blockDim.x)
+            if (bt.lcnt[i]) atomicAdd(&a.counters[i], bt.lcnt[i]);
+    if (a.lds_tally)
+        for (uint32_t i = threadIdx.x; i < a.n_bins; i += blockDim.x)
+            if (bt.ltally[i]) atomicAdd(&a.counts[i], (unsigned long long)bt.ltally[i]);
+}
+
+// Wave-private run of queue slots [q, q_end), reserved QUEUE_CHUNK at a time with one
+// atomic on the queue length.  Slots a wave leaves unused are marked empty when it exits.
+struct QRun {
+    uint64_t q = 0, q_end = 0;
+};
+
+// Lanes whose atom thermalised in the last flight hand it to the diffusive queue and become
+// free.  Slots come from the wave's run (a hand-over may continue into a fresh run).  Their
+// collisions are counted here; thermalisation itself is counted when the walk ends.
+__device__ __forceinline__ void hand_over(const TransportArgs& a, uint32_t pid, int seg, Particle<float>& p,
+                                          LaneAcc& acc, QRun& Q, int lane, uint64_t lt_mask)
+{
+    const uint64_t T = __ballot(p.st == ST_DIFFUSIVE);
+    if (T == 0) return;
+    const uint64_t n = (uint64_t)__popcll(T);
+    const uint64_t rem = Q.q_end - Q.q;
+    uint64_t fresh = 0;
+    if (rem < n) {
+        unsigned long long b = 0;
+        if (lane == 0) b = atomicAdd((unsigned long long*)&a.qstate[1], (unsigned long long)QUEUE_CHUNK);
+        fresh = __shfl(b, 0);
+    }
+    if (p.st == ST_DIFFUSIVE) {
+        const uint64_t rank = (uint64_t)__popcll(T & lt_mask);
+        const uint64_t slot = rank < rem ? Q.q + rank : fresh + (rank - rem);   // < queue capacity
+        ThermRec r;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            r.x[i] = p.x[i];
+            r.xc[i] = p.xc[i];
+        }
+        r.E = p.E;
+        r.pid = pid;
+        r.seg = (uint32_t)seg;
+        r.e = p.e;
+        r.pad[0] = r.pad[1] = 0u;
+        a.queue[slot] = r;
+        acc.c[C_COLLISIONS] += p.ncoll;
+        p.st = ST_DEAD;
+    }
+    if (rem < n) {
+        Q.q = fresh + (n - rem);
+        Q.q_end = fresh + QUEUE_CHUNK;
+    } else {
+        Q.q += n;
+    }
+}
+
+// Mark the wave's unused reserved slots as empty (pid ~0).
+__device__ __forceinline__ void close_run(const TransportArgs& a, const QRun& Q, int lane)
+{
+    if (Q.q + (uint64_t)lane < Q.q_end) a.queue[Q.q + lane].pid = 0xFFFFFFFFu;
+}
+
+// Ballistic flights of the lanes in segment S (uniform: its constants stay in scalar
+// registers) until the wave should refill or has no ballistic lane left.
+__device__ __forceinline__ void ballistic_loop(const TransportArgs& a, const BlockTally& bt, const SegDev<float>& S,
+                                               uint32_t pid, int seg, Particle<float>& p, LaneAcc& acc, QRun& Q,
+                                               bool drained, int lane, uint64_t lt_mask)
 {
     for (;;) {
-        if (p.st == MODE) {
-            const Term t = (MODE == ST_BALLISTIC) ? step_mode<float, ST_BALLISTIC>(S, a.tab, a.k0, a.k1, pid, a.cap, p)
-                                                  : step_diffusive_ball(S, a.k0, a.k1, pid, a.cap, p);
+        if (p.st == ST_BALLISTIC) {
+            const Term t = step_mode<float, ST_BALLISTIC>(S, a.tab, a.k0, a.k1, pid, a.cap, p);
             if (t.state != HIT_NONE) terminate(a, bt, S, pid, p, t, acc);
         }
-        const uint64_t M = __ballot(p.st == MODE);
-        if (M == 0) break;
-        if (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) break;
-        if (drained && __popcll(__ballot(p.st != ST_DEAD)) <= COOP_MAX) break;   // cooperative walks
-        if (MODE == ST_BALLISTIC && __popcll(M) < a.ballistic_min && __ballot(p.st == ST_DIFFUSIVE) != 0) break;
+        hand_over(a, pid, seg, p, acc, Q, lane, lt_mask);
+        if (__ballot(p.st == ST_BALLISTIC) == 0) break;
+        if (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_ballistic) break;
     }
 }
 
@@ -126,37 +234,32 @@ __device__ __forceinline__ void diffusive_loop(const TransportArgs& a, const Blo
         const uint64_t H = __ballot(held);
         const uint64_t M = __ballot(p.st == ST_DIFFUSIVE);
         bool stop = M == 0 || (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) ||
-                    (drained && __popcll(__ballot(p.st != ST_DEAD)) <= COOP_MAX);
+                    (drained && __popcll(M) <= COOP_MAX);
         if (H != 0 && (stop || H == M || __popcll(H) >= DEFER_MIN)) {
             if (held) {
                 held = false;
                 const Term t = diffusive_resolve(S, p);
                 if (t.state != HIT_NONE) terminate(a, bt, S, pid, p, t, acc);
             }
-            stop = __ballot(p.st == ST_DIFFUSIVE) == 0 ||
-                   (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) ||
-                   (drained && __popcll(__ballot(p.st != ST_DEAD)) <= COOP_MAX);
+            const uint64_t M2 = __ballot(p.st == ST_DIFFUSIVE);
+            stop = M2 == 0 || (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) ||
+                   (drained && __popcll(M2) <= COOP_MAX);
         }
         if (stop) break;
     }
 }
 
+// Ballistic phase of one round: every ticket of the round, from launch until the atom ends
+// on a surface, escapes, or thermalises (then it is queued for the diffusive phase).
 // Dynamic LDS: per-segment counters (u64, when lds_counters) then the tally (u32, when lds_tally).
 // At most 96 VGPRs: five waves per SIMD hide the latency of the transcendental and
 // integer-multiply chains.
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5)))
-k_transport32(TransportArgs a, const SegDev<float>* __restrict__ segs)
+k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
 {
     extern __shared__ unsigned long long lds[];
     BlockTally bt;
-    bt.lcnt = lds;
-    bt.ltally = (uint32_t*)(lds + (a.lds_counters ? (size_t)a.n_seg * N_COUNTERS : 0));
-    if (a.lds_counters)
-        for (int i = threadIdx.x; i < a.n_seg * N_COUNTERS; i += blockDim.x) bt.lcnt[i] = 0;
-    if (a.lds_tally)
-        for (uint32_t i = threadIdx.x; i < a.n_bins; i += blockDim.x) bt.ltally[i] = 0;
-    __syncthreads();
-
+    lds_setup(a, bt, lds);
     const int lane = threadIdx.x & 63;
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     Particle<float> p;
@@ -165,92 +268,122 @@ k_transport32(TransportArgs a, const SegDev<float>* __restrict__ segs)
     uint32_t pid = 0;
     int seg = 0;
     LaneAcc acc;
-    bool drained = false;   // wave-uniform: the ticket space is exhausted
-    // Wave-private run of tickets [tk, tk_end), claimed TICKET_CHUNK at a time with one
-    // atomic, so that refills rarely touch the global counter.
-    uint64_t tk = 0, tk_end = 0;
-
+    Tickets T;
+    QRun Q;
     for (;;) {
-        // refill: dead lanes take consecutive tickets of the wave's run (ballot + mbcnt prefix)
         const uint64_t dead = __ballot(p.st == ST_DEAD);
         const int n_dead = __popcll(dead);
-        if (!drained && n_dead > 0 && (n_dead >= a.refill_min || n_dead == 64)) {
-            if (tk == tk_end) {
-                unsigned long long base = 0;
-                if (lane == 0) base = atomicAdd((unsigned long long*)a.ticket, (unsigned long long)TICKET_CHUNK);
-                base = __shfl(base, 0);
-                if (base >= a.total) {
-                    drained = true;
-                } else {
-                    tk = base;
-                    tk_end = (base + TICKET_CHUNK < a.total) ? base + TICKET_CHUNK : a.total;
+        if (!T.drained && n_dead > 0 && (n_dead >= a.refill_ballistic || n_dead == 64)) {
+            const uint64_t my = claim(T, &a.qstate[0], a.total, dead, lane, lt_mask);
+            if (my != ~0ull) {
+                const uint64_t g = a.tbase + my;
+                int lo = 0, hi = a.n_seg;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (a.tfirst[mid] <= g) lo = mid; else hi = mid;
                 }
-            }
-            const uint64_t avail = tk_end - tk;
-            const uint64_t take = avail < (uint64_t)n_dead ? avail : (uint64_t)n_dead;
-            const uint64_t base = tk;
-            tk += take;
-            if (p.st == ST_DEAD) {
-                const uint64_t rank = (uint64_t)__popcll(dead & lt_mask);
-                const uint64_t my = base + rank;
-                if (rank < take) {
-                    int lo = 0, hi = a.n_seg;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (a.tfirst[mid] <= my) lo = mid; else hi = mid;
-                    }
-                    const int sg = (int)a.torder[lo];
-                    pid = (uint32_t)(my - a.tfirst[lo]);
-                    if (sg != acc.seg) {
-                        flush_acc(a, bt, acc);
-                        acc.seg = sg;
-                    }
-                    seg = sg;
-                    start(segs[seg], a.k0, a.k1, pid, p);
-                    acc.c[C_LAUNCHED] += 1;
+                const int sg = (int)a.torder[lo];
+                pid = (uint32_t)(g - a.tfirst[lo]);
+                if (sg != acc.seg) {
+                    flush_acc(a, bt, acc);
+                    acc.seg = sg;
                 }
+                seg = sg;
+                start(segs[seg], a.k0, a.k1, pid, p);
+                acc.c[C_LAUNCHED] += 1;
             }
         }
         const uint64_t B = __ballot(p.st == ST_BALLISTIC);
-        const uint64_t D = __ballot(p.st == ST_DIFFUSIVE);
-        if ((B | D) == 0) {
-            if (drained) break;
+        if (B == 0) {
+            if (T.drained) break;
             continue;
         }
-        // Last histories of a drained wave: each thermalised lane is walked by the whole
-        // wave (up to 64 steps per pass) before the regular step below.
-        if (drained && __popcll(B | D) <= COOP_MAX) {
+        const int s0 = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)B) - 1);
+        if (__ballot(p.st == ST_BALLISTIC && seg != s0) == 0) {
+            ballistic_loop(a, bt, segs[s0], pid, s0, p, acc, Q, T.drained, lane, lt_mask);
+        } else {
+            // lanes of several segments: one flight with per-lane constants
+            if (p.st == ST_BALLISTIC) {
+                const SegDev<float>& s = segs[seg];
+                const Term t = step_mode<float, ST_BALLISTIC>(s, a.tab, a.k0, a.k1, pid, a.cap, p);
+                if (t.state != HIT_NONE) terminate(a, bt, s, pid, p, t, acc);
+            }
+            hand_over(a, pid, seg, p, acc, Q, lane, lt_mask);
+        }
+    }
+    close_run(a, Q, lane);
+    lds_flush(a, bt, acc);
+}
+
+// Diffusive phase of one round: the walks of the atoms queued by the ballistic phase.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5)))
+k_diffusive32(TransportArgs a, const SegDev<float>* __restrict__ segs)
+{
+    extern __shared__ unsigned long long lds[];
+    BlockTally bt;
+    lds_setup(a, bt, lds);
+    const uint64_t total = a.qstate[1];      // written by the ballistic phase of this round
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    Particle<float> p;
+    p.st = ST_DEAD;
+    p.e = p.ndiff = p.ncoll = 0;
+    uint32_t pid = 0;
+    int seg = 0;
+    LaneAcc acc;
+    Tickets T;
+    for (;;) {
+        const uint64_t dead = __ballot(p.st == ST_DEAD);
+        const int n_dead = __popcll(dead);
+        if (!T.drained && n_dead > 0 && (n_dead >= a.refill_min || n_dead == 64)) {
+            const uint64_t my = claim(T, &a.qstate[2], total, dead, lane, lt_mask);
+            const uint32_t qpid = my != ~0ull ? a.queue[my].pid : 0xFFFFFFFFu;
+            if (qpid != 0xFFFFFFFFu) {                 // empty slots (left unused by a wave) are skipped
+                const ThermRec r = a.queue[my];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    p.x[i] = r.x[i];
+                    p.xc[i] = r.xc[i];
+                }
+                p.E = r.E;
+                p.e = r.e;
+                p.ndiff = 0;
+                p.ncoll = 0;
+                p.r2 = -1.f;           // no clearance ball yet: the first step is tested
+                p.st = ST_DIFFUSIVE;
+                pid = r.pid;
+                const int sg = (int)r.seg;
+                if (sg != acc.seg) {
+                    flush_acc(a, bt, acc);
+                    acc.seg = sg;
+                }
+                seg = sg;
+            }
+        }
+        const uint64_t D = __ballot(p.st == ST_DIFFUSIVE);
+        if (D == 0) {
+            if (T.drained) break;
+            continue;
+        }
+        // Last walks of a drained wave: each is walked by the whole wave (up to 64 steps per
+        // pass) before the regular step below.
+        if (T.drained && __popcll(D) <= COOP_MAX) {
             for (uint64_t W = D; W != 0; W &= W - 1) {
                 const int L = __ffsll((unsigned long long)W) - 1;
                 coop_walk(segs[__builtin_amdgcn_readlane(seg, L)], a.k0, a.k1, a.cap, pid, p, L, lane);
             }
         }
-        // One kind of event at a time: ballistic flights only once enough lanes are
-        // ballistic (or nothing else is left), so that rare ballistic lanes do not drag the
-        // long collision path into most iterations of a thermalised wave.
-        const int mode = (B != 0 && (__popcll(B) >= a.ballistic_min || D == 0)) ? ST_BALLISTIC : ST_DIFFUSIVE;
-        const uint64_t Mm = (mode == ST_BALLISTIC) ? B : D;
-        const int s0 = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)Mm) - 1);
-        if (__ballot(p.st == mode && seg != s0) == 0) {
-            const SegDev<float>& S = segs[s0];
-            if (mode == ST_BALLISTIC) uniform_loop<ST_BALLISTIC>(a, bt, S, pid, p, acc, drained);
-            else diffusive_loop(a, bt, S, pid, p, acc, drained);
-        } else if (p.st == mode) {
-            // lanes of several segments: one flight with per-lane constants
+        const int s0 = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)D) - 1);
+        if (__ballot(p.st == ST_DIFFUSIVE && seg != s0) == 0) {
+            diffusive_loop(a, bt, segs[s0], pid, p, acc, T.drained);
+        } else if (p.st == ST_DIFFUSIVE) {
+            // lanes of several segments: one step with per-lane constants
             const SegDev<float>& s = segs[seg];
-            const Term t = (mode == ST_BALLISTIC) ? step_mode<float, ST_BALLISTIC>(s, a.tab, a.k0, a.k1, pid, a.cap, p)
-                                                  : step_diffusive_ball(s, a.k0, a.k1, pid, a.cap, p);
+            const Term t = step_diffusive_ball(s, a.k0, a.k1, pid, a.cap, p);
             if (t.state != HIT_NONE) terminate(a, bt, s, pid, p, t, acc);
         }
     }
-    flush_acc(a, bt, acc);
-    __syncthreads();
-    if (a.lds_counters)
-        for (int i = threadIdx.x; i < a.n_seg * N_COUNTERS; i += blockDim.x)
-            if (bt.lcnt[i]) atomicAdd(&a.counters[i], bt.lcnt[i]);
-    if (a.lds_tally)
-        for (uint32_t i = threadIdx.x; i < a.n_bins; i += blockDim.x)
-            if (bt.ltally[i]) atomicAdd(&a.counts[i], (unsigned long long)bt.ltally[i]);
+    lds_flush(a, bt, acc);
 }
 
 __global__ void __launch_bounds__(256) k_transport64(const SegDev<double>* __restrict__ segp, TabDev<double> tab,
@@ -288,14 +421,18 @@ __global__ void __launch_bounds__(256) k_transport64(const SegDev<double>* __res
     }
 }
 
-// Zero the outputs and the ticket counter (a kernel, so that it can sit in a graph).
-__global__ void k_zero(unsigned long long* counts, uint64_t n_counts, unsigned long long* counters, uint64_t n_counters,
-                       uint64_t* ticket)
+// Zero the outputs (a kernel, so that it can sit in a graph).
+__global__ void k_zero(unsigned long long* counts, uint64_t n_counts, unsigned long long* counters, uint64_t n_counters)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_counts; i += stride) counts[i] = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_counters; i += stride) counters[i] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && ticket) *ticket = 0;
+}
+
+// Reset a round's ticket counters and queue length.
+__global__ void k_round_reset(uint64_t* qstate)
+{
+    if (threadIdx.x < 3) qstate[threadIdx.x] = 0;
 }
 
 // profiles = counts / (N_seg * bin area); FP64.
@@ -314,12 +451,12 @@ __global__ void k_normalize(const unsigned long long* __restrict__ counts, const
     }
 }
 
-static int launch_zero_and_tail(Plan* P, uint64_t* d_counts, uint64_t* d_counters, uint64_t* ticket, hipStream_t st)
+static int launch_zero(Plan* P, uint64_t* d_counts, uint64_t* d_counters, hipStream_t st)
 {
     const uint64_t n = P->n_bins_total;
     const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 + 1 : 4096);
     hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, (unsigned long long*)d_counts, n,
-                       (unsigned long long*)d_counters, (uint64_t)P->n_seg * N_COUNTERS, ticket);
+                       (unsigned long long*)d_counters, (uint64_t)P->n_seg * N_COUNTERS);
     SPX_HIP(hipGetLastError());
     return SPX_OK;
 }
@@ -348,15 +485,25 @@ int occupancy_transport32(const Plan* P, int threads, int* blocks_per_cu)
 {
     bool lc, lt;
     const size_t smem = transport32_lds(P, &lc, &lt);
-    SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_transport32, threads, smem));
+    int b1 = 0, b2 = 0;
+    SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_ballistic32, threads, smem));
+    SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_diffusive32, threads, smem));
+    *blocks_per_cu = b1 < b2 ? b1 : b2;
     return SPX_OK;
 }
 
+// The batched kernels' entry points, to find their nodes in a captured graph.
+const void* ballistic_kernel() { return (const void*)k_ballistic32; }
+const void* diffusive_kernel() { return (const void*)k_diffusive32; }
+
+// Rounds of a ticket space of `total` tickets: as few as ROUND_MAX allows, of equal size.
+uint64_t rounds_of(uint64_t total) { return total == 0 ? 0 : (total + ROUND_MAX - 1) / ROUND_MAX; }
+
 int launch_transport32(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
                        spx_record* d_records, hipStream_t st, const uint64_t* tfirst, uint64_t total, int blocks,
-                       int threads, int refill_min, int ballistic_min)
+                       int threads, int refill_min, int refill_ballistic, const hipEvent_t* events)
 {
-    SPX_TRY(launch_zero_and_tail(P, d_counts, d_counters, P->d_ticket, st));
+    SPX_TRY(launch_zero(P, d_counts, d_counters, st));
     TransportArgs a;
     a.segs = P->d_seg32;
     a.tab.theta = P->d_theta32;
@@ -366,25 +513,43 @@ int launch_transport32(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_c
     a.tab.xs = (float)((P->params.table_ne - 1) / ((P->params.log_eps_hi - P->params.log_eps_lo) * 3.321928094887362));
     a.tfirst = tfirst;
     a.torder = P->d_torder;
-    a.ticket = P->d_ticket;
+    a.queue = P->d_queue;
+    a.qstate = P->d_qstate;
     a.counts = (unsigned long long*)d_counts;
     a.counters = (unsigned long long*)d_counters;
     a.records = d_records;
-    a.total = total;
     a.k0 = (uint32_t)seed;
     a.k1 = (uint32_t)(seed >> 32);
     a.cap = P->params.event_cap;
     a.n_seg = P->n_seg;
     a.refill_min = refill_min;
-    a.ballistic_min = ballistic_min;
+    a.refill_ballistic = refill_ballistic;
     a.n_bins = (uint32_t)P->n_bins_total;
     bool lc, lt;
     const size_t smem = transport32_lds(P, &lc, &lt);
     a.lds_counters = lc ? 1 : 0;
     a.lds_tally = lt ? 1 : 0;
-    hipLaunchKernelGGL(k_transport32, dim3(blocks), dim3(threads), smem, st, a,
-                       (const SegDev<float>*)P->d_seg32);
-    SPX_HIP(hipGetLastError());
+    const uint64_t n_rounds = rounds_of(total);
+    const uint64_t per_round = n_rounds ? (total + n_rounds - 1) / n_rounds : 0;
+    // every queue slot a round can reserve: its atoms plus at most one unused run per wave
+    const uint64_t waves = (uint64_t)blocks * (uint64_t)((threads + 63) / 64);
+    if (n_rounds && per_round + waves * QUEUE_CHUNK > P->queue_cap) {
+        set_error("internal: round larger than the thermalisation queue");
+        return SPX_ESTATE;
+    }
+    for (uint64_t r = 0; r < n_rounds; ++r) {
+        a.tbase = r * per_round;
+        a.total = (a.tbase + per_round < total) ? per_round : total - a.tbase;
+        if (events) SPX_HIP(hipEventRecord(events[3 * r], st));
+        hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(64), 0, st, P->d_qstate);
+        SPX_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_ballistic32, dim3(blocks), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
+        SPX_HIP(hipGetLastError());
+        if (events) SPX_HIP(hipEventRecord(events[3 * r + 1], st));
+        hipLaunchKernelGGL(k_diffusive32, dim3(blocks), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
+        SPX_HIP(hipGetLastError());
+        if (events) SPX_HIP(hipEventRecord(events[3 * r + 2], st));
+    }
     if (d_profiles) SPX_TRY(launch_normalize(P, d_counts, d_profiles, st));
     return SPX_OK;
 }
@@ -392,7 +557,7 @@ int launch_transport32(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_c
 int launch_transport64(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
                        spx_record* d_records, hipStream_t st)
 {
-    SPX_TRY(launch_zero_and_tail(P, d_counts, d_counters, nullptr, st));
+    SPX_TRY(launch_zero(P, d_counts, d_counters, st));
     TabDev<double> tab;
     tab.theta = P->d_theta64;
     tab.betamax = P->d_betamax64;

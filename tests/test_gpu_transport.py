@@ -223,3 +223,27 @@ def test_edge_cases():
     assert rec["events"].max() == 3
     m = match_stats(rec, ref["records"], 1e-3)
     assert m["frac"] >= 0.99, m
+
+
+def test_phase_times():
+    """The two kernels' device times of the last run (events recorded between them)."""
+    say("phase times")
+    plan = spx.Plan([si.single_ni(2.0, 20000), si.single_ni(0.0, 20000)], PARAMS)
+    with pytest.raises(spx.SpxError):
+        plan.phase_times()                      # no run yet
+    bufs = plan.allocate(profiles=False)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    plan.run_into(4, bufs)
+    ev1.record()
+    tb, td = plan.phase_times()
+    torch.cuda.synchronize()
+    total = ev0.elapsed_time(ev1)
+    say(f"  ballistic {tb:.3f} ms, diffusive {td:.3f} ms, step {total:.3f} ms")
+    assert tb > 0 and td > 0 and tb + td <= total * 1.001 + 0.05
+    # FP64 plans have no batched phases
+    p64 = spx.Plan([si.single_ni(0.5, 100)], PARAMS, precision=64)
+    p64.run(seed=1)
+    with pytest.raises(spx.SpxError):
+        p64.phase_times()
