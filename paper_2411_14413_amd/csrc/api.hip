@@ -513,14 +513,16 @@ static int run(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters,
 static int autotune(Plan* P, hipStream_t st)
 {
     const int n = P->n_seg;
-    // The tuning sample keeps the plan's mix: the same fraction of every segment, sized so
-    // that each resident lane gets ~48 histories: a persistent launch ends in a tail of the longest
-    // histories whose share of the time shrinks with the work per lane, and a sample with too
-    // little work per lane favours shapes that only shorten that tail.
+    // The tuning sample keeps the plan's mix: the same fraction of every segment, the whole
+    // plan up to 4e7 particles, else at least ~48 histories per resident lane: a persistent
+    // launch ends in a tail of the longest histories whose share of the time shrinks with the
+    // work per lane, and a sample with too little work per lane favours shapes that only
+    // shorten that tail.
     int bpc_max = 0;
     SPX_TRY(occupancy_transport32(P, 256, &bpc_max));
     const double lanes = (double)std::max(1, bpc_max) * P->n_cu * 256.0;
-    const double frac = std::min(1.0, 48.0 * lanes / (double)std::max<uint64_t>(1, P->n_particles_total));
+    const double frac =
+        std::min(1.0, std::max(48.0 * lanes, 4e7) / (double)std::max<uint64_t>(1, P->n_particles_total));
     std::vector<uint64_t> tf(n + 1, 0);
     std::vector<uint32_t> order(n);
     std::iota(order.begin(), order.end(), 0u);
@@ -541,7 +543,7 @@ static int autotune(Plan* P, hipStream_t st)
     float best = 1e30f;
     int bb = P->blocks, bt = P->threads, br = P->refill_min, bm = P->refill_ballistic;
     const int thread_opts[] = {256, 512, 1024};
-    const int mode_opts[][2] = {{4, 4}, {8, 8}, {16, 16}};
+    const int mode_opts[][2] = {{4, 4}, {4, 16}, {8, 8}};   // (refill_min, refill_ballistic)
     for (int t : thread_opts) {
         if (rc != SPX_OK) break;
         int bpc = 0;

@@ -579,26 +579,34 @@ __device__ __forceinline__ Term step_diffusive_ball(const SegDev<float>& s, uint
 // is held (direction in p.d, length in p.r2: the ball is rebuilt after the test anyway) and
 // sets held.  diffusive_resolve finishes a held step exactly as step_diffusive_ball would
 // have.  Steps, events and positions are those of step_diffusive_ball.
-__device__ __forceinline__ void diffusive_substep(const SegDev<float>& s, uint4 w, bool odd, Particle<float>& p,
-                                                  bool& held)
+//
+// One diffusive sub-step from block w (the odd or the even half) for a lane where `active`;
+// straight-line code ending in selects, so that inactive lanes keep their state and no
+// branch splits the wave.
+__device__ __forceinline__ void diffusive_substep(const SegDev<float>& s, uint4 w, bool odd, bool active,
+                                                  Particle<float>& p, bool& held)
 {
     uint32_t k[3];
     diffusive_codes(w, odd, k);
-    p.e += 1;
     float dir[3], v[3];
     const float ell = diffusive_draw(s, k, dir);   // diffusive only after a gas collision
     step_vector(ell, dir, v);
     float y[3], t[3];
     kahan_try(p.x, p.xc, v, y, t);
-    if (ball_holds(t, p.d, p.r2)) {
-        kahan_commit(p.x, p.xc, y, t);
-        ++p.ndiff;
-    } else {
+    const bool ok = ball_holds(t, p.d, p.r2);
+    const bool commit = active && ok, hold = active && !ok;
+    float xn[3] = {p.x[0], p.x[1], p.x[2]}, xcn[3] = {p.xc[0], p.xc[1], p.xc[2]};
+    kahan_commit(xn, xcn, y, t);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) p.d[i] = dir[i];
-        p.r2 = ell;
-        held = true;
+    for (int i = 0; i < 3; ++i) {
+        p.x[i] = commit ? xn[i] : p.x[i];
+        p.xc[i] = commit ? xcn[i] : p.xc[i];
+        p.d[i] = hold ? dir[i] : p.d[i];
     }
+    p.r2 = hold ? ell : p.r2;
+    p.e += active ? 1u : 0u;
+    p.ndiff += commit ? 1u : 0u;
+    held = held || hold;
 }
 
 __device__ __forceinline__ Term diffusive_advance(const SegDev<float>& s, uint32_t k0, uint32_t k1, uint32_t pid,
@@ -606,11 +614,10 @@ __device__ __forceinline__ Term diffusive_advance(const SegDev<float>& s, uint32
 {
     if (p.e >= cap) return Term{HIT_ESCAPED, -1};
     const uint4 w = diffusive_block(pid, p.e + 1, s.cfgcat, k0, k1);
-    if (((p.e + 1) & 1u) == 0) {
-        diffusive_substep(s, w, false, p, held);
-        if (held || p.e >= cap) return Term{HIT_NONE, -1};   // a capped history escapes at its next step
-    }
-    diffusive_substep(s, w, true, p, held);
+    // the even step of the block (if the next event is even), then its odd step unless the
+    // even one is held or the cap is reached (a capped history escapes at its next step)
+    diffusive_substep(s, w, false, ((p.e + 1) & 1u) == 0, p, held);
+    diffusive_substep(s, w, true, !held && p.e < cap, p, held);
     return Term{HIT_NONE, -1};
 }
 
