@@ -61,10 +61,10 @@ OPS = dict(
 # Peak: the FP32 vector rate of the MI355X, 157.3 TFLOP/s = 78.6e12 FMA/s, i.e. 128 lanes per
 # CU per clock (256 CUs, 2.4 GHz); one slot = one full-rate 32-bit lane operation.
 PEAK_ALU = 256 * 128 * 2.4e9
-# HBM bytes per launch of each kernel from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per
-# dispatch, scaled by a copy probe) on the default workload; None until taken for the current
-# kernels.
-TRAFFIC = {}
+# HBM bytes per launch of each kernel on the default workload from rocprofv3: FETCH_SIZE x 2.000
+# + WRITE_SIZE x 1.000 (KiB per dispatch; factors from a 1 GiB copy and fill).  Valid for the
+# kernels they were taken on; set to None when a kernel changes.
+TRAFFIC = {"k_diffusive32": (320941 * 2.0 + 37170) * 1024, "k_ballistic32": (1633 * 2.0 + 712945) * 1024}
 
 
 def algorithmic_ops(counters):
