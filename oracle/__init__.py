@@ -31,7 +31,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-SEG_LEN = 48
+RT_MAX = 256
+SEG_LEN = 52 + 2 * RT_MAX
 P_LEN = 8
 REC = 8
 STATE_DEPOSITED, STATE_WALL, STATE_ESCAPED = 1, 2, 3
@@ -205,6 +206,13 @@ def segments(cfgs: Sequence) -> np.ndarray:
             r[38:43] = [cat.U_s, cat.E_i, cat.k_cut, cat.mass, cat.Z]
             r[43] = cat.n_particles
             r[44] = off
+            prof = np.asarray(cat.rt_profile if cat.rt_profile is not None else np.zeros((0, 2)),
+                              dtype=np.float64).reshape(-1, 2)
+            if len(prof) > RT_MAX:
+                raise ValueError(f"racetrack profile with more than {RT_MAX} nodes")
+            r[45] = len(prof)
+            r[46:52] = cat.cos_coeff
+            r[52:52 + 2 * len(prof)] = prof.ravel()
             off += g.nu * g.nv
             rows.append(r)
     return np.ascontiguousarray(np.stack(rows))

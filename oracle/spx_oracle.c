@@ -318,7 +318,12 @@ enum {
     S_CFG = 0, S_CATH, S_CH_R, S_CH_ZLO, S_CH_ZHI, S_P, S_T, S_MG, S_ZG, S_GASMOTION,
     S_SUB_C = 10, S_SUB_N = 13, S_SUB_U = 16, S_HALF_U = 19, S_HALF_V, S_SHAPE, S_NU, S_NV,
     S_CAT_C = 24, S_CAT_N = 27, S_CAT_U = 30, S_CAT_R = 33, S_RT_MU, S_RT_SIG, S_RT_LO, S_RT_HI,
-    S_US = 38, S_EI, S_KCUT, S_MS, S_ZS, S_N, S_BINOFF, S_LEN = 48
+    S_US = 38, S_EI, S_KCUT, S_MS, S_ZS, S_N, S_BINOFF,
+    S_RT_N = 45,               /* 0: truncated-normal racetrack; else nodes of a measured profile */
+    S_COS = 46,                /* c_0 .. c_5 of the emission law */
+    S_RT = 52,                 /* (r_i, depth_i), i < RT_MAX */
+    RT_MAX = 256,
+    S_LEN = S_RT + 2 * RT_MAX
 };
 /* Flat parameter layout. */
 enum { P_THETA_MIN = 0, P_ETH_KT, P_EVENT_CAP, P_NE, P_NS, P_LOGLO, P_LOGHI, P_LEN = 8 };
@@ -330,6 +335,11 @@ typedef struct {
     int shape, nu, nv;
     double cat_c[3], cat_n[3], cat_u[3], cat_v[3], cat_R;
     double rt_mu, rt_sig, PhiA, QB, dPhi;
+    int rt_n;                             /* measured racetrack: nodes (0 = truncated normal) */
+    double rt_r[RT_MAX], rt_d[RT_MAX];    /* radius, erosion depth */
+    double rt_F[RT_MAX];                  /* integral_0^{r_i} depth(s) s ds */
+    double cosc[6], cos_norm;             /* emission law sum c_i mu^i; norm = sum c_i / (i + 1) */
+    int cos_pure;                         /* the cosine law c = (0, 1, 0, 0, 0, 0) */
     double Us, Emax, smax, Lambda;
     double Ms, Mg, mu_red, eps_per_eV, a_mm;
     double n_mm3, kT, vth, vg;           /* vth = sqrt(kT/Mg) per Cartesian component; vg = sqrt(2kT/Mg) */
@@ -394,6 +404,15 @@ static double seg_sigma(const seg_t* s, const tab_t* tb, double eps)
     return OR_PI * b * b;
 }
 
+/* integral over s in [r_i, r_i + t] of depth(s) s, depth linear on the node interval i */
+static double rt_piece(const seg_t* s, int i, double t)
+{
+    const double dr = s->rt_r[i + 1] - s->rt_r[i];
+    const double m = (s->rt_d[i + 1] - s->rt_d[i]) / dr;
+    const double d0 = s->rt_d[i], r0 = s->rt_r[i];
+    return d0 * r0 * t + (d0 + m * r0) * t * t / 2.0 + m * t * t * t / 3.0;
+}
+
 static void seg_init(const double* r, const double* prm, const tab_t* tb, seg_t* s)
 {
     memset(s, 0, sizeof(*s));
@@ -416,6 +435,26 @@ static void seg_init(const double* r, const double* prm, const tab_t* tb, seg_t*
     s->PhiA = or_norm_cdf(al);
     s->QB = or_norm_cdf(-be);                       /* 1 - Phi(beta), without cancellation */
     s->dPhi = or_norm_cdf(be) - s->PhiA;
+
+    /* Measured racetrack: erosion depth linear between the nodes; the start radius has a
+     * density proportional to depth(r) r (area element of an axisymmetric target). */
+    s->rt_n = (int)r[S_RT_N];
+    for (int i = 0; i < s->rt_n; ++i) {
+        s->rt_r[i] = r[S_RT + 2 * i];
+        s->rt_d[i] = r[S_RT + 2 * i + 1];
+    }
+    if (s->rt_n > 0) s->rt_F[0] = 0.0;
+    for (int i = 0; i + 1 < s->rt_n; ++i)
+        s->rt_F[i + 1] = s->rt_F[i] + rt_piece(s, i, s->rt_r[i + 1] - s->rt_r[i]);
+
+    /* Emission law: density of mu = cos(theta) on [0, 1] proportional to sum c_i mu^i. */
+    s->cos_norm = 0.0;
+    s->cos_pure = 1;
+    for (int i = 0; i < 6; ++i) {
+        s->cosc[i] = r[S_COS + i];
+        s->cos_norm += s->cosc[i] / (i + 1);
+        if (s->cosc[i] != (i == 1 ? 1.0 : 0.0)) s->cos_pure = 0;
+    }
 
     /* Thompson energy with cut-off: the ion is the working-gas ion (Ar+), M_i = gas mass. */
     s->Ms = r[S_MS]; s->Mg = r[S_MG];
@@ -476,29 +515,77 @@ static double flight_length(const seg_t* s, const tab_t* tb, double E, double rn
 /* ------------------------------------------------------------------------- */
 /* Launch: racetrack start point, Thompson energy, cosine direction.         */
 /* ------------------------------------------------------------------------- */
+/* Start radius of a measured racetrack: r = F^{-1}(RN F(R)) with F(r) the integral of
+ * depth(s) s from 0 to r.  The node interval holding the target is the first whose end
+ * value reaches it (RN > 0, so it carries positive weight); inside it F is a cubic, inverted
+ * by bisection to the resolution of the doubles. */
+static double racetrack_radius(const seg_t* s, double rn)
+{
+    const double target = rn * s->rt_F[s->rt_n - 1];
+    int i = 0;
+    while (i < s->rt_n - 2 && s->rt_F[i + 1] < target) ++i;
+    const double want = target - s->rt_F[i];
+    double lo = 0.0, hi = s->rt_r[i + 1] - s->rt_r[i];
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (rt_piece(s, i, mid) < want) lo = mid; else hi = mid;
+    }
+    return s->rt_r[i] + 0.5 * (lo + hi);
+}
+
+/* cos(theta) of the emission law: G(mu) = sum c_i mu^(i+1)/(i+1) = RN G(1), by bisection on [0, 1]. */
+static double emission_mu(const seg_t* s, double rn)
+{
+    const double want = rn * s->cos_norm;
+    double lo = 0.0, hi = 1.0;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double g = 0.0, p = mid;
+        for (int i = 0; i < 6; ++i) {
+            g += s->cosc[i] * p / (i + 1);
+            p *= mid;
+        }
+        if (g < want) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
 static void launch(const seg_t* s, uint64_t seed, uint32_t pid, double x[3], double d[3], double* E)
 {
     double u[4], u4[4];
     draw4(seed, pid, 0, s->cfgcat, 0, u);
     draw4(seed, pid, 0, s->cfgcat, 1, u4);
-    /* start radius by inverse CDF of the truncated normal; the upper half uses the complement */
-    double z;
-    const double P = s->PhiA + u[0] * s->dPhi;
-    if (P <= 0.5) {
-        z = or_norm_inv(P);
+    double rr;
+    if (s->rt_n > 0) {
+        rr = racetrack_radius(s, u[0]);
     } else {
-        const double Q = s->QB + (1.0 - u[0]) * s->dPhi;
-        z = -or_norm_inv(Q);
+        /* start radius by inverse CDF of the truncated normal; the upper half uses the complement */
+        double z;
+        const double P = s->PhiA + u[0] * s->dPhi;
+        if (P <= 0.5) {
+            z = or_norm_inv(P);
+        } else {
+            const double Q = s->QB + (1.0 - u[0]) * s->dPhi;
+            z = -or_norm_inv(Q);
+        }
+        rr = s->rt_mu + s->rt_sig * z;
     }
-    const double rr = s->rt_mu + s->rt_sig * z;
     const double psi = 2.0 * OR_PI * u[1];
     for (int i = 0; i < 3; ++i) x[i] = s->cat_c[i] + rr * (cos(psi) * s->cat_u[i] + sin(psi) * s->cat_v[i]);
     /* Thompson: F(E) = [E/(E+U_s)]^2 / [E_max/(E_max+U_s)]^2 inverted */
     const double sE = sqrt(u[2]) * s->smax;
     *E = s->Us * sE / (1.0 - sE);
-    /* cosine law: cos(theta) = sqrt(RN), azimuth uniform */
-    const double mu = sqrt(u[3]);
-    const double st = sqrt(1.0 - u[3]);
+    /* polar angle from the emission law (cosine law: cos(theta) = sqrt(RN)), azimuth uniform */
+    double mu, st;
+    if (s->cos_pure) {
+        mu = sqrt(u[3]);
+        st = sqrt(1.0 - u[3]);
+    } else {
+        mu = emission_mu(s, u[3]);
+        st = sqrt((1.0 - mu) * (1.0 + mu));
+    }
     const double phi = 2.0 * OR_PI * u4[0];
     for (int i = 0; i < 3; ++i)
         d[i] = mu * s->cat_n[i] + st * (cos(phi) * s->cat_u[i] + sin(phi) * s->cat_v[i]);

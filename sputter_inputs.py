@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field, replace
-from typing import List, Sequence, Tuple
+from typing import List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -87,8 +87,11 @@ class Cathode:
     k_cut: float = 1.0             # E_max = k * Lambda * E_i - U_s
     mass: float = 58.69
     Z: int = 28
-    cos_coeff: Tuple[float, ...] = (0.0, 1.0, 0.0, 0.0, 0.0, 0.0)
+    cos_coeff: Tuple[float, ...] = (0.0, 1.0, 0.0, 0.0, 0.0, 0.0)   # emission law sum c_i cos^i
     n_particles: int = 100_000
+    # measured racetrack: radial erosion-depth profile [(r mm, depth), ...] from r = 0, radii
+    # increasing; None = the truncated normal above
+    rt_profile: Optional[Sequence[Tuple[float, float]]] = None
 
 
 @dataclass
@@ -129,6 +132,44 @@ def single_ni(pressure: float = 0.5, n_particles: int = 100_000, gas_motion: int
 def single_ni_legs(n_particles: int = 10_000_000) -> List[Config]:
     """The three chambers of the single-target batch: 0.5 Pa, 0 Pa and 2 Pa."""
     return [single_ni(0.5, n_particles), single_ni(0.0, n_particles), single_ni(2.0, n_particles)]
+
+
+# ---------------------------------------------------------------------------
+# Measured-racetrack and emission-law inputs.
+# ---------------------------------------------------------------------------
+# An emission law with an under-cosine (heart-shaped) polar distribution, sum c_i cos^i theta,
+# non-negative on [0, 90 deg]: the kind of six-coefficient law the model accepts besides the
+# plain cosine.
+UNDER_COSINE = (0.1, 0.5, 1.0, -0.6, 0.0, 0.0)
+
+
+def measured_racetrack(seed: int = 0, radius: float = 25.4, step: float = 0.5,
+                       depth: float = 1.8) -> List[Tuple[float, float]]:
+    """A synthetic profilometry scan of an eroded target along its diameter, folded into a
+    radial erosion-depth profile (the racetrack is taken as axisymmetric).  The scan has the
+    main groove at r = 15 mm (sd 3 mm), a shallow inner groove at r = 6 mm and seeded
+    measurement noise; negative readings are clipped to zero.  Returns [(r, depth)] from
+    r = 0 to the target radius."""
+    rng = np.random.default_rng(seed)
+    K = int(math.floor(radius / step + 1e-9))
+    xs = np.concatenate([[-radius], step * np.arange(-K, K + 1), [radius]])
+    r = np.abs(xs)
+    prof = depth * (np.exp(-(r - 15.0) ** 2 / (2 * 3.0 ** 2)) + 0.12 * np.exp(-(r - 6.0) ** 2 / (2 * 2.0 ** 2)))
+    scan = np.clip(prof + rng.normal(0.0, 0.02 * depth, size=xs.size), 0.0, None)
+    # fold: mean of the readings at -r and +r
+    nodes = np.unique(np.round(r, 9))
+    out = []
+    for rk in nodes:
+        out.append((float(rk), float(scan[np.isclose(r, rk)].mean())))
+    return out
+
+
+def with_launch(cfg: Config, rt_profile=None, cos_coeff=None) -> Config:
+    """Copy of cfg whose cathodes use the given racetrack profile and/or emission law."""
+    cats = [replace(c, rt_profile=rt_profile if rt_profile is not None else c.rt_profile,
+                    cos_coeff=tuple(cos_coeff) if cos_coeff is not None else c.cos_coeff)
+            for c in cfg.cathodes]
+    return Config(chamber=cfg.chamber, grid=cfg.grid, cathodes=cats)
 
 
 # ---------------------------------------------------------------------------
