@@ -86,6 +86,13 @@ def workload(name, scale=1.0):
         return (si.single_ni_legs(n),
                 f"single Ni target (50.8 mm), Ar 0.5 / 0 / 2 Pa, 300 K, 100x100 mm substrate at 100 mm, "
                 f"50x50 bins, 3 chambers x {n:.0e} particles in one launch")
+    if name == "legs_measured":
+        n = int(1e7 * scale)
+        prof = si.measured_racetrack(seed=0)
+        return ([si.with_launch(c, prof, si.UNDER_COSINE) for c in si.single_ni_legs(n)],
+                f"single Ni target (50.8 mm) with a measured racetrack profile and an under-cosine "
+                f"six-coefficient emission law, Ar 0.5 / 0 / 2 Pa, 300 K, 100x100 mm substrate at 100 mm, "
+                f"50x50 bins, 3 chambers x {n:.0e} particles in one launch")
     if name == "quaternary":
         cfg = si.quaternary()
         return [cfg], "four confocal cathodes Ni/Pd/Pt/Ru, tilt 25 deg, 150 mm, Ar 0.5 Pa, 100 mm wafer 200x200 bins, 2.3e7 particles"
@@ -151,7 +158,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="legs", choices=["legs", "quaternary", "sweep"])
+    ap.add_argument("--workload", default="legs", choices=["legs", "legs_measured", "quaternary", "sweep"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")

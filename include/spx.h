@@ -66,7 +66,7 @@ typedef struct spx_cathode {
     double normal[3];      /* unit normal pointing into the gas */
     double u_axis[3];      /* unit in-plane axis; v = normal x u_axis */
     double radius;         /* target radius, mm; the disc absorbs on both faces */
-    double rt_mu, rt_sigma;/* racetrack start radius ~ normal(rt_mu, rt_sigma) ... */
+    double rt_mu, rt_sigma;/* racetrack (rt_n == 0): start radius ~ normal(rt_mu, rt_sigma) ... */
     double rt_lo, rt_hi;   /* ... truncated to [rt_lo, rt_hi], azimuth uniform */
     double U_s;            /* surface binding energy, eV (Thompson distribution) */
     double E_i;            /* incident ion energy, eV */
@@ -74,9 +74,16 @@ typedef struct spx_cathode {
                               M_i = gas mass (the working-gas ion) */
     double mass;           /* sputtered atom mass, u */
     int32_t Z;             /* sputtered atom number */
-    int32_t reserved0;
-    double cos_coeff[6];   /* emission law sum c_i cos^i; only {0,1,0,0,0,0} (cosine) is accepted */
+    int32_t rt_n;          /* 0: racetrack from rt_mu .. rt_hi; 2 .. 256: nodes of rt_profile */
+    double cos_coeff[6];   /* nascent angular law d2Y/dOmega = sum_i c_i cos^i(theta) (Methods, "The
+                              SIMTRA model"); must be >= 0 for theta in [0, 90 deg] with
+                              sum c_i/(i+1) > 0; {0,1,0,0,0,0} is the cosine law */
     uint64_t n_particles;  /* particles launched from this cathode, < 2^32 */
+    const double* rt_profile; /* measured racetrack (Methods, "The SIMTRA model" and "Racetrack
+                              measurement"): host array [rt_n][2] of (radius mm, erosion depth >= 0),
+                              radii strictly increasing, first >= 0, last <= radius, positive weight;
+                              depth linear between nodes, start radius with density depth(r) r,
+                              azimuth uniform.  Deep-copied; NULL when rt_n == 0 */
 } spx_cathode;
 
 /* Vacuum chamber: absorbing cylinder on the z axis with a homogeneous gas in thermal
@@ -136,9 +143,11 @@ typedef struct spx_plan spx_plan;
  * device (Moliere potential, Firsov screening length; theta_cm(log10 eps, b/b_max)
  * and b_max(eps) where theta_cm = theta_min), synchronously.  Rejects: pressure < 0,
  * T <= 0, zero cathodes, all cathodes with n_particles == 0, n_particles >= 2^32,
- * a cathode or substrate outside the chamber, nu*nv > 2^24 or < 1, rt_lo >= rt_hi,
- * E_max <= 0, masses <= 0, a non-cosine emission law, non-unit or non-orthogonal
- * axes, more than 2^24 configurations.  *out is set only on success. */
+ * a cathode or substrate outside the chamber, nu*nv > 2^24 or < 1, rt_lo >= rt_hi (rt_n == 0),
+ * an invalid racetrack profile (rt_n == 1 or > 256, radii not increasing, outside [0, radius],
+ * negative depths, zero weight), E_max <= 0, masses <= 0, an emission law negative somewhere on
+ * [0, 90 deg] or with zero integral, non-unit or non-orthogonal axes, more than 2^24
+ * configurations.  *out is set only on success. */
 int spx_plan_create(const spx_config* h_cfgs, int32_t n_cfgs, const spx_params* h_params, spx_plan** out);
 
 /* Sizes of spx_run's outputs: total tally bins over all segments, counters

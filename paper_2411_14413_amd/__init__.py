@@ -67,7 +67,7 @@ class Plan:
     pressure, T, gas_mass, gas_Z, gas_motion), ``grid`` (center, normal, u_axis,
     half_u, half_v, shape, nu, nv) and ``cathodes`` (each: center, normal, u_axis,
     radius, rt_mu, rt_sigma, rt_lo, rt_hi, U_s, E_i, k_cut, mass, Z, cos_coeff,
-    n_particles).  ``precision`` 32 = batched FP32 transport (one persistent
+    n_particles, optionally rt_profile: [(r, depth), ...] of a measured racetrack).  ``precision`` 32 = batched FP32 transport (one persistent
     launch), 64 = plain FP64 comparator (one launch per segment).
     """
 
@@ -93,6 +93,15 @@ class Plan:
                 K.U_s, K.E_i, K.k_cut, K.mass, K.Z = c.U_s, c.E_i, c.k_cut, c.mass, int(c.Z)
                 K.cos_coeff = (ctypes.c_double * 6)(*[float(x) for x in c.cos_coeff])
                 K.n_particles = int(c.n_particles)
+                prof = getattr(c, "rt_profile", None)
+                if prof is not None:
+                    flat = [float(v) for pt in prof for v in pt]
+                    arr = (ctypes.c_double * len(flat))(*flat)
+                    self._keep.append(arr)
+                    K.rt_n = len(flat) // 2
+                    K.rt_profile = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+                else:
+                    K.rt_n = 0
             self._keep.append(cats)
             C.n_cathodes = len(cfg.cathodes)
             C.cathodes = ctypes.cast(cats, ctypes.POINTER(N.Cathode))

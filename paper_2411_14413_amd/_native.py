@@ -25,7 +25,8 @@ class Cathode(ctypes.Structure):
                 ("rt_mu", ctypes.c_double), ("rt_sigma", ctypes.c_double), ("rt_lo", ctypes.c_double),
                 ("rt_hi", ctypes.c_double), ("U_s", ctypes.c_double), ("E_i", ctypes.c_double),
                 ("k_cut", ctypes.c_double), ("mass", ctypes.c_double), ("Z", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("cos_coeff", ctypes.c_double * 6), ("n_particles", ctypes.c_uint64)]
+                ("rt_n", ctypes.c_int32), ("cos_coeff", ctypes.c_double * 6), ("n_particles", ctypes.c_uint64),
+                ("rt_profile", ctypes.POINTER(ctypes.c_double))]
 
 
 class Chamber(ctypes.Structure):

@@ -108,15 +108,45 @@ static int validate(const spx_config* cfgs, int n_cfgs, const spx_params* p)
             double kv[3];
             cross(K.normal, K.u_axis, kv);
             if (!disc_inside(ch, K.center, K.u_axis, kv, K.radius)) return fail(wk + "target disc outside the chamber");
-            if (!(K.rt_sigma > 0.0) || !(K.rt_lo < K.rt_hi) || K.rt_lo < 0.0 || K.rt_hi > K.radius)
-                return fail(wk + "racetrack needs sigma > 0 and 0 <= rt_lo < rt_hi <= radius");
+            if (K.rt_n == 0) {
+                if (!(K.rt_sigma > 0.0) || !(K.rt_lo < K.rt_hi) || K.rt_lo < 0.0 || K.rt_hi > K.radius)
+                    return fail(wk + "racetrack needs sigma > 0 and 0 <= rt_lo < rt_hi <= radius");
+            } else {
+                if (K.rt_n < 2 || K.rt_n > RT_MAX_NODES || !K.rt_profile)
+                    return fail(wk + "racetrack profile needs 2.." + std::to_string(RT_MAX_NODES) + " nodes");
+                double wsum = 0.0;
+                for (int i = 0; i < K.rt_n; ++i) {
+                    const double r = K.rt_profile[2 * i], d = K.rt_profile[2 * i + 1];
+                    if (!std::isfinite(r) || !std::isfinite(d) || d < 0.0 || r < 0.0 || r > K.radius ||
+                        (i > 0 && !(r > K.rt_profile[2 * i - 2])))
+                        return fail(wk + "racetrack profile: radii must increase within [0, radius], depths >= 0");
+                    if (i > 0) wsum += (d + K.rt_profile[2 * i - 1]) * (r - K.rt_profile[2 * i - 2]);
+                }
+                if (!(wsum > 0.0)) return fail(wk + "racetrack profile has no erosion");
+            }
             if (!(K.U_s > 0.0) || !(K.E_i > 0.0) || !(K.k_cut > 0.0)) return fail(wk + "U_s, E_i, k_cut must be > 0");
             if (!(K.mass > 0.0) || K.Z < 1) return fail(wk + "mass and Z must be positive");
             const double lam = 4.0 * K.mass * ch.gas_mass / ((K.mass + ch.gas_mass) * (K.mass + ch.gas_mass));
             if (!(K.k_cut * lam * K.E_i - K.U_s > 0.0)) return fail(wk + "E_max = k Lambda E_i - U_s must be > 0");
-            const double cosine[6] = {0, 1, 0, 0, 0, 0};
-            for (int i = 0; i < 6; ++i)
-                if (K.cos_coeff[i] != cosine[i]) return fail(wk + "only the cosine emission law {0,1,0,0,0,0} is supported");
+            {
+                double norm = 0.0;
+                for (int i = 0; i < 6; ++i) {
+                    if (!std::isfinite(K.cos_coeff[i])) return fail(wk + "emission coefficients must be finite");
+                    norm += K.cos_coeff[i] / (i + 1);
+                }
+                bool neg = false;
+                for (int j = 0; j <= 4096; ++j) {
+                    const double mu = j / 4096.0;
+                    double f = 0.0, pw = 1.0;
+                    for (int i = 0; i < 6; ++i) {
+                        f += K.cos_coeff[i] * pw;
+                        pw *= mu;
+                    }
+                    neg = neg || f < 0.0;
+                }
+                if (neg || !(norm > 0.0))
+                    return fail(wk + "emission law sum c_i cos^i must be >= 0 on [0, 90 deg] with a positive integral");
+            }
             if (K.n_particles >= (1ull << 32)) return fail(wk + "n_particles must be < 2^32");
             total += K.n_particles;
         }
@@ -162,6 +192,12 @@ static void derive(Plan* P, const spx_config* cfgs, int n_cfgs)
             s.zhi = ch.z_hi - s.z_mid;
             s.rt_mu = K.rt_mu;
             s.rt_sig = K.rt_sigma;
+            // measured racetrack: cumulative weight F_i = integral_0^{r_i} depth(s) s ds at the nodes
+            for (int i = 0; i < K.rt_n; ++i) {
+                s.rt_r.push_back(K.rt_profile[2 * i]);
+                s.rt_d.push_back(K.rt_profile[2 * i + 1]);
+            }
+            for (int i = 0; i < 6; ++i) s.cosc[i] = K.cos_coeff[i];
             const double al = (K.rt_lo - K.rt_mu) / K.rt_sigma, be = (K.rt_hi - K.rt_mu) / K.rt_sigma;
             s.PhiA = norm_cdf(al);
             s.QB = norm_cdf(-be);
@@ -259,6 +295,16 @@ template <typename R> static SegDev<R> to_device(const Plan* P, const SegHost& s
     d.nv = s.nv;
     d.gas_motion = s.gas_motion;
     d.vacuum = s.n_mm3 > 0.0 ? 0 : 1;
+    d.rt = nullptr;                          // set once the racetrack tables are on the device
+    d.rt_n = (int32_t)s.rt_r.size();
+    double norm = 0.0;
+    bool pure = true;
+    for (int i = 0; i < 6; ++i) {
+        norm += s.cosc[i] / (i + 1);
+        pure = pure && s.cosc[i] == (i == 1 ? 1.0 : 0.0);
+    }
+    for (int i = 0; i < 6; ++i) d.cosk[i] = (R)(s.cosc[i] / ((i + 1) * norm));
+    d.cos_pure = pure ? 1 : 0;
     d.cfgcat = ((uint32_t)s.cfg << 8) | (uint32_t)s.cath;
     d.bin_off = s.bin_off;
     d.first_rec = s.first_rec;
@@ -283,7 +329,8 @@ static void release(Plan* P)
     if (P->graph_exec) (void)hipGraphExecDestroy(P->graph_exec);
     if (P->graph) (void)hipGraphDestroy(P->graph);
     void* ptrs[] = {P->d_theta64, P->d_betamax64, P->d_theta32, P->d_betamax32, P->d_seg32,   P->d_seg64,
-                    P->d_tfirst,  P->d_torder,    P->d_qstate,  P->d_queue,     P->d_bin_off, P->d_seg_norm};
+                    P->d_tfirst,  P->d_torder,    P->d_qstate,  P->d_queue,     P->d_bin_off, P->d_seg_norm,
+                    P->d_rt32,    P->d_rt64};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (hipEvent_t e : P->phase_events) (void)hipEventDestroy(e);
@@ -363,6 +410,48 @@ static int create(const spx_config* cfgs, int n_cfgs, const spx_params* prm, Pla
     for (const auto& s : P->seg) {
         s32.push_back(to_device<float>(P, s));
         s64.push_back(to_device<double>(P, s));
+    }
+    // measured racetracks: per node interval the normalised cumulative weight and the cubic
+    // of the weight integral_r^{r+t} depth(s) s ds (depth linear on the interval), FP64 on the host
+    std::vector<RtNode<double>> rt64;
+    std::vector<size_t> rt_off(n, 0);
+    for (int k = 0; k < n; ++k) {
+        const auto& sg = P->seg[k];
+        const int m = (int)sg.rt_r.size();
+        rt_off[k] = rt64.size();
+        if (m == 0) continue;
+        std::vector<double> F(m, 0.0), p1(m, 0.0), p2(m, 0.0), p3(m, 0.0);
+        for (int i = 0; i + 1 < m; ++i) {
+            const double dr = sg.rt_r[i + 1] - sg.rt_r[i], sl = (sg.rt_d[i + 1] - sg.rt_d[i]) / dr;
+            const double d0 = sg.rt_d[i], r0 = sg.rt_r[i];
+            p1[i] = d0 * r0;
+            p2[i] = (d0 + sl * r0) / 2.0;
+            p3[i] = sl / 3.0;
+            F[i + 1] = F[i] + ((p3[i] * dr + p2[i]) * dr + p1[i]) * dr;
+        }
+        const double Z = F[m - 1];
+        for (int i = 0; i < m; ++i) {
+            const bool last = i + 1 == m;
+            rt64.push_back(RtNode<double>{sg.rt_r[i], last ? 1.0 : F[i] / Z, p1[i] / Z, p2[i] / Z, p3[i] / Z,
+                                          last ? 0.0 : sg.rt_r[i + 1] - sg.rt_r[i]});
+        }
+    }
+    if (!rt64.empty()) {
+        std::vector<RtNode<float>> rt32;
+        for (const auto& q : rt64)
+            rt32.push_back(RtNode<float>{(float)q.r, (float)q.C, (float)q.p1, (float)q.p2, (float)q.p3, (float)q.dr});
+        if (dalloc(&P->d_rt32, rt32.size()) != SPX_OK || dalloc(&P->d_rt64, rt64.size()) != SPX_OK ||
+            hipMemcpy(P->d_rt32, rt32.data(), sizeof(RtNode<float>) * rt32.size(), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(P->d_rt64, rt64.data(), sizeof(RtNode<double>) * rt64.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            set_error("copying the racetrack tables to the device failed");
+            release(P);
+            return SPX_EDEVICE;
+        }
+        for (int k = 0; k < n; ++k)
+            if (!P->seg[k].rt_r.empty()) {
+                s32[k].rt = P->d_rt32 + rt_off[k];
+                s64[k].rt = P->d_rt64 + rt_off[k];
+            }
     }
     // ticket order: highest pressure (longest histories) first
     std::vector<uint32_t> order(n);

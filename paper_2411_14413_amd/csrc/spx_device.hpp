@@ -136,6 +136,13 @@ template <> __device__ __forceinline__ double m_inf<double>() { return __builtin
 // Per-segment constants, derived on the host in double precision.
 // Positions are in the chamber-centred frame: z' = z - z_mid.
 // --------------------------------------------------------------------------
+// One node interval of a measured racetrack: start radius r, normalised cumulative weight C
+// at r, and the cubic H(t) = ((p3 t + p2) t + p1) t giving the weight of [r, r + t] for
+// t <= dr (depth linear on the interval, density depth(r) r).  The last node has C = 1.
+template <typename R> struct RtNode {
+    R r, C, p1, p2, p3, dr;
+};
+
 template <typename R> struct SegDev {
     R cat_c[3], cat_n[3], cat_u[3], cat_v[3];
     R cat_R2;
@@ -145,6 +152,8 @@ template <typename R> struct SegDev {
     R half_u, half_v, inv_du, inv_dv, sub_R2;
     R ch_R2, zlo, zhi;
     R rt_mu, rt_sig, PhiA, QB, dPhi;      // racetrack truncated normal
+    const RtNode<R>* rt;                  // measured racetrack (rt_n nodes), else nullptr
+    R cosk[6];                            // emission law: G(mu) = sum cosk_i mu^(i+1) rises from 0 to 1
     R Us, smax;                           // Thompson inverse CDF
     R two_over_Ms, half_Ms;               // v = sqrt(2E/Ms), E = Ms v^2 / 2
     R Ms_frac, Mg_frac;                   // Ms/(Ms+Mg), Mg/(Ms+Mg)
@@ -156,7 +165,8 @@ template <typename R> struct SegDev {
     R E_th, lam_th;
     R z_mid;                              // chamber-frame origin along z (world z = z' + z_mid)
     int32_t shape, nu, nv, gas_motion;
-    int32_t vacuum, pad0;
+    int32_t vacuum, rt_n;
+    int32_t cos_pure, pad0;               // cos_pure: the cosine law, cos(theta) = sqrt(RN)
     uint32_t cfgcat;                      // (config << 8) | cathode: third Philox counter word
     uint32_t pad1;
     uint64_t bin_off;                     // first bin of this segment in the tally
@@ -208,6 +218,46 @@ template <typename R> __device__ __forceinline__ R dot3(const R* a, const R* b)
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
+// Bisection steps that shrink an interval to the precision of R.
+template <typename R> struct Bisect;
+template <> struct Bisect<float> { static constexpr int steps = 26; };
+template <> struct Bisect<double> { static constexpr int steps = 60; };
+
+// Start radius on a measured racetrack: r = F^-1(RN) with F the normalised weight of
+// [0, r]: the node interval with C_i < RN <= C_{i+1} (binary search), then bisection on the
+// interval's cubic.
+template <typename R> __device__ __forceinline__ R racetrack_radius(const SegDev<R>& s, R u)
+{
+    const RtNode<R>* T = s.rt;
+    int lo = 0, hi = s.rt_n - 1;          // C[lo] < u <= C[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (T[mid].C < u) lo = mid; else hi = mid;
+    }
+    const RtNode<R> n = T[lo];
+    const R want = u - n.C;
+    R a = (R)0, b = n.dr;
+    for (int it = 0; it < Bisect<R>::steps; ++it) {
+        const R mid = (R)0.5 * (a + b);
+        const R h = ((n.p3 * mid + n.p2) * mid + n.p1) * mid;
+        if (h < want) a = mid; else b = mid;
+    }
+    return n.r + (R)0.5 * (a + b);
+}
+
+// cos(theta) of a general emission law: G(mu) = RN on [0, 1] by bisection.
+template <typename R> __device__ __forceinline__ R emission_mu(const SegDev<R>& s, R u)
+{
+    R a = (R)0, b = (R)1;
+    for (int it = 0; it < Bisect<R>::steps; ++it) {
+        const R m = (R)0.5 * (a + b);
+        const R g =
+            m * (s.cosk[0] + m * (s.cosk[1] + m * (s.cosk[2] + m * (s.cosk[3] + m * (s.cosk[4] + m * s.cosk[5])))));
+        if (g < u) a = m; else b = m;
+    }
+    return (R)0.5 * (a + b);
+}
+
 // --------------------------------------------------------------------------
 // Launch (event 0): sub-block 0 -> u0..u3, sub-block 1 -> u4.
 // --------------------------------------------------------------------------
@@ -216,17 +266,22 @@ __device__ __forceinline__ void launch(const SegDev<R>& s, uint4 r0, uint4 r1, R
 {
     const R u0 = u01<R>(r0.x), u1 = u01<R>(r0.y), u2 = u01<R>(r0.z), u3 = u01<R>(r0.w);
     const R u4 = u01<R>(r1.x);
-    // racetrack radius: inverse CDF of the truncated normal; the upper half takes the
-    // complement so that no precision is lost near 1
-    R z;
-    const R P = s.PhiA + u0 * s.dPhi;
-    if (P <= (R)0.5) {
-        z = m_ninv(P);
+    R rr;
+    if (s.rt_n > 0) {
+        rr = racetrack_radius(s, u0);
     } else {
-        const R Q = s.QB + ((R)1 - u0) * s.dPhi;
-        z = -m_ninv(Q);
+        // racetrack radius: inverse CDF of the truncated normal; the upper half takes the
+        // complement so that no precision is lost near 1
+        R z;
+        const R P = s.PhiA + u0 * s.dPhi;
+        if (P <= (R)0.5) {
+            z = m_ninv(P);
+        } else {
+            const R Q = s.QB + ((R)1 - u0) * s.dPhi;
+            z = -m_ninv(Q);
+        }
+        rr = s.rt_mu + s.rt_sig * z;
     }
-    const R rr = s.rt_mu + s.rt_sig * z;
     R sp, cp;
     m_sincos2pi(u1, &sp, &cp);
 #pragma unroll
@@ -234,8 +289,15 @@ __device__ __forceinline__ void launch(const SegDev<R>& s, uint4 r0, uint4 r1, R
     // Thompson energy: [E/(E+U_s)]^2 proportional to RN up to the cut-off
     const R se = m_sqrt(u2) * s.smax;
     E = m_div(s.Us * se, (R)1 - se);
-    // cosine emission: cos(theta) = sqrt(RN)
-    const R mu = m_sqrt(u3), st = m_sqrt((R)1 - u3);
+    // emission law: the cosine law inverts in closed form, cos(theta) = sqrt(RN)
+    R mu, st;
+    if (s.cos_pure) {
+        mu = m_sqrt(u3);
+        st = m_sqrt((R)1 - u3);
+    } else {
+        mu = emission_mu(s, u3);
+        st = m_sqrt(((R)1 - mu) * ((R)1 + mu));
+    }
     R sf, cf;
     m_sincos2pi(u4, &sf, &cf);
 #pragma unroll

@@ -43,6 +43,8 @@ struct SegHost {
     double n_mm3, kT, vth, vg, E_th, lam_th;
     int gas_motion;
     double pressure;
+    std::vector<double> rt_r, rt_d;   // measured racetrack nodes (empty: truncated normal)
+    double cosc[6];                   // emission law coefficients
     uint64_t N, bin_off, first_rec;
     double cost;          // relative expected work per particle (ticket ordering)
 };
@@ -87,6 +89,7 @@ constexpr uint64_t ROUND_MAX = 1ull << 25;   // tickets per round: a 1.6 GB queu
 constexpr uint64_t QUEUE_CHUNK = 64;         // queue slots a wave reserves per atomic
 constexpr uint64_t QUEUE_SLACK_WAVES = 8192;  // waves that may leave slots unused (32 per CU, 256 CUs)
 constexpr size_t LDS_COUNTERS_MAX = 16384;   // bytes: up to 292 segments
+constexpr int RT_MAX_NODES = 256;             // nodes of a measured racetrack profile
 constexpr uint64_t TICKET_CHUNK = 64;        // tickets a wave claims per global atomic
 constexpr int DEFER_MIN = 8;                  // held diffusive steps that trigger a wave's surface tests
 constexpr int COOP_MAX = 8;                   // drained waves with at most this many live lanes walk cooperatively
@@ -126,6 +129,8 @@ struct spx_plan {
     float* d_betamax32 = nullptr;
     spx::SegDev<float>* d_seg32 = nullptr;
     spx::SegDev<double>* d_seg64 = nullptr;
+    spx::RtNode<float>* d_rt32 = nullptr;     // measured racetracks of all segments
+    spx::RtNode<double>* d_rt64 = nullptr;
     uint64_t* d_tfirst = nullptr;
     uint32_t* d_torder = nullptr;
     spx::ThermRec* d_queue = nullptr;       // thermalised atoms of a round (FP32 plans)

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
 def test_header_struct_sizes_match_binding():
     from paper_2411_14413_amd import _native as N
     assert ctypes.sizeof(N.Record) == 48
-    assert ctypes.sizeof(N.Cathode) == 8 * (9 + 1 + 4 + 4) + 8 + 8 * 6 + 8
+    assert ctypes.sizeof(N.Cathode) == 8 * (9 + 1 + 4 + 4) + 8 + 8 * 6 + 8 + 8
     assert ctypes.sizeof(N.Chamber) == 8 * 6 + 8
     assert ctypes.sizeof(N.Grid) == 8 * 11 + 16
 
@@ -48,7 +48,13 @@ def _create(cfgs, **kw):
     (lambda c: setattr(c.cathodes[0], "rt_lo", 30.0), "racetrack"),
     (lambda c: setattr(c.cathodes[0], "mass", -1.0), "mass"),
     (lambda c: setattr(c.cathodes[0], "E_i", 1.0), "E_max"),
-    (lambda c: setattr(c.cathodes[0], "cos_coeff", (0.5, 0.5, 0, 0, 0, 0)), "cosine"),
+    (lambda c: setattr(c.cathodes[0], "cos_coeff", (0, 1, 0, 0, 0, -2)), "emission law"),
+    (lambda c: setattr(c.cathodes[0], "cos_coeff", (0, 0, 0, 0, 0, 0)), "emission law"),
+    (lambda c: setattr(c.cathodes[0], "rt_profile", [(0.0, 1.0)]), "racetrack profile"),
+    (lambda c: setattr(c.cathodes[0], "rt_profile", [(0.0, 1.0), (5.0, 1.0), (4.0, 1.0)]), "racetrack profile"),
+    (lambda c: setattr(c.cathodes[0], "rt_profile", [(0.0, 1.0), (5.0, -1.0)]), "racetrack profile"),
+    (lambda c: setattr(c.cathodes[0], "rt_profile", [(0.0, 1.0), (30.0, 1.0)]), "racetrack profile"),
+    (lambda c: setattr(c.cathodes[0], "rt_profile", [(0.0, 0.0), (5.0, 0.0)]), "no erosion"),
     (lambda c: setattr(c.cathodes[0], "center", (190.0, 0.0, 100.0)), "outside"),
     (lambda c: setattr(c.grid, "nu", 0), "nu"),
     (lambda c: setattr(c.grid, "normal", (0.0, 0.0, -2.0)), "orthonormal"),

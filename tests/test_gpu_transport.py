@@ -247,3 +247,53 @@ def test_phase_times():
     p64.run(seed=1)
     with pytest.raises(spx.SpxError):
         p64.phase_times()
+
+
+def _measured_launch_batch():
+    prof = si.measured_racetrack(seed=0)
+    return [si.with_launch(si.single_ni(0.5, 20000), prof, si.UNDER_COSINE),
+            si.with_launch(si.single_ni(0.0, 20000), [(0.0, 0.0), (10.0, 0.0), (12.0, 1.0), (18.0, 1.0),
+                                                     (20.0, 0.0), (25.4, 0.0)], (0, 0, 1, 0, 0, 0)),
+            si.with_launch(si.single_ni(2.0, 2000), prof, (1, 0, 0, 0, 0, 0)),
+            si.with_launch(si.quaternary(0.5, 25.0, 150.0, [3000, 1000, 2000, 1500]), prof, si.UNDER_COSINE)]
+
+
+@pytest.mark.parametrize("precision, tol, need", [(32, 1e-3, 0.99), (64, 1e-6, 0.999)])
+def test_measured_racetrack_and_emission_law_parity(precision, tol, need):
+    """Launch from a measured racetrack profile with six-coefficient emission laws: per-particle
+    parity with the oracle, integer identities."""
+    cfgs = _measured_launch_batch()
+    say(f"measured racetrack / emission law parity, precision {precision}")
+    ref = oracle.run(cfgs, PARAMS, seed=21, records=True)
+    plan = spx.Plan(cfgs, PARAMS, precision=precision)
+    out = plan.run(seed=21, records=True)
+    torch.cuda.synchronize()
+    rec = spx.records_to_numpy(out["records"])
+    first = _first(plan)
+    for k in range(plan.n_segments):
+        sl = slice(first[k], first[k + 1])
+        m = match_stats(rec[sl], ref["records"][sl], tol)
+        say(f"  seg {k}: {m}")
+        assert m["frac"] >= need, (k, m)
+    hist = records_histogram(rec, [nv * nu for nv, nu in plan.shapes], first, plan.n_bins)
+    for k in range(plan.n_segments):
+        assert np.array_equal(out["counts_seg"][k].cpu().numpy().ravel(), hist[k])
+
+
+def test_zero_pressure_measured_launch_against_line_of_sight():
+    from test_oracle_transport import analytic_bin_fractions_general
+    n = 10_000_000
+    cfg = si.with_launch(si.single_ni(0.0, n), si.measured_racetrack(seed=0), si.UNDER_COSINE)
+    say("0 Pa, measured racetrack, under-cosine law: 1e7 particles vs the integrated line of sight")
+    plan = spx.Plan([cfg], PARAMS)
+    out = plan.run(seed=0)
+    torch.cuda.synchronize()
+    counts = out["counts_seg"][0].cpu().numpy().astype(np.float64)
+    exp = n * analytic_bin_fractions_general(cfg)
+    z = (counts - exp) / np.sqrt(exp)
+    dof = counts.size
+    chi2 = float((z ** 2).sum())
+    say(f"  chi2/dof = {chi2 / dof:.4f}, max|z| = {np.abs(z).max():.2f}")
+    assert chi2 < dof + 4.5 * math.sqrt(2 * dof)
+    assert np.abs(z).max() < 5.0
+    assert abs(counts.sum() - exp.sum()) < 4.5 * math.sqrt(exp.sum())
