@@ -34,7 +34,7 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 RT_MAX = 256
 SEG_LEN = 52 + 2 * RT_MAX
 P_LEN = 8
-REC = 8
+REC = 9
 STATE_DEPOSITED, STATE_WALL, STATE_ESCAPED = 1, 2, 3
 COUNTER_NAMES = ("launched", "deposited", "wall", "escaped", "collisions", "diffusive_steps", "thermalized")
 
@@ -350,6 +350,51 @@ def normalize(counts: np.ndarray, n_launched: int, grid) -> np.ndarray:
     """Deposition profile per launched atom and mm^2: count / (N * bin area)."""
     area = (2.0 * grid.half_u / grid.nu) * (2.0 * grid.half_v / grid.nv)
     return np.asarray(counts, dtype=np.float64) / (float(n_launched) * area)
+
+
+# Arrival tallies (the Monte Carlo's energy and angle distributions of arriving atoms):
+# energy in 60 bins with edges 10^(-3 + k/10) eV, incidence angle in 90 bins of 1 degree.
+N_ARRIVAL_E, N_ARRIVAL_A = 60, 90
+ESUM_SCALE = 2.0 ** 24          # energy sums as integers in units of 2^-24 eV
+
+
+def arrival_edges():
+    """(energy edges [61] eV, cosines of the angle edges [91]: cos(k deg))."""
+    k = np.arange(N_ARRIVAL_E + 1)
+    return 10.0 ** (-3.0 + k / 10.0), np.cos(np.deg2rad(np.arange(N_ARRIVAL_A + 1)))
+
+
+def arrival_bins(E, cos_in, e_edges=None, c_edges=None):
+    """Energy bin = #{k in 1..59 : E >= e_k}; angle bin = #{k in 1..89 : cos_in <= cos(k deg)}
+    (under- and overflow fall into the end bins)."""
+    if e_edges is None:
+        e_edges, c_edges = arrival_edges()
+    E = np.asarray(E)
+    c = np.asarray(cos_in)
+    be = (E[:, None] >= e_edges[None, 1:N_ARRIVAL_E]).sum(axis=1)
+    ba = (c[:, None] <= c_edges[None, 1:N_ARRIVAL_A]).sum(axis=1)
+    return be, ba
+
+
+def arrival_tallies(records, first, n_bins_seg, bin_off):
+    """Per segment energy and angle histograms of the deposits, and per tally bin the sum of
+    their energies as integers rint(E * 2^24), from [n, 9] records (segment-major; first[k]
+    = first record of segment k)."""
+    n_seg = len(first) - 1
+    hE = np.zeros((n_seg, N_ARRIVAL_E), dtype=np.uint64)
+    hA = np.zeros((n_seg, N_ARRIVAL_A), dtype=np.uint64)
+    esum = np.zeros(int(bin_off[-1] + n_bins_seg[-1]) if n_seg else 0, dtype=np.uint64)
+    for k in range(n_seg):
+        r = records[first[k]:first[k + 1]]
+        dep = r[:, 3] == 1
+        if not dep.any():
+            continue
+        be, ba = arrival_bins(r[dep, 7], r[dep, 8])
+        hE[k] = np.bincount(be, minlength=N_ARRIVAL_E).astype(np.uint64)
+        hA[k] = np.bincount(ba, minlength=N_ARRIVAL_A).astype(np.uint64)
+        q = np.rint(r[dep, 7] * ESUM_SCALE).astype(np.uint64)
+        np.add.at(esum, bin_off[k] + r[dep, 4].astype(np.int64), q)
+    return hE, hA, esum
 
 
 def area_centres(n_areas: int = 342, pitch: float = 4.5) -> np.ndarray:

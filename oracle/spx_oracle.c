@@ -742,6 +742,7 @@ static void diffusive_draw(const seg_t* s, const double u[3], double d[3], doubl
 /* ------------------------------------------------------------------------- */
 typedef struct {
     double x[3], E;
+    double cos_in;          /* deposits: cosine of the incidence angle (-d . substrate normal); else 0 */
     int state, bin;
     uint32_t events, ndiff, ncoll;
     int thermalized;
@@ -758,6 +759,7 @@ static void trace(const seg_t* s, const tab_t* tb, uint64_t seed, uint32_t pid, 
     uint32_t e = 1;
     res->state = OR_ESCAPED;
     res->bin = -1;
+    res->cos_in = 0.0;
     for (;; ++e) {
         if (e > tb->event_cap) { res->state = OR_ESCAPED; e = tb->event_cap; break; }
         double u[4];
@@ -774,6 +776,7 @@ static void trace(const seg_t* s, const tab_t* tb, uint64_t seed, uint32_t pid, 
             for (int i = 0; i < 3; ++i) x[i] += h.t * d[i];
             res->state = h.state;
             res->bin = h.bin;
+            if (h.state == OR_DEPOSITED) res->cos_in = -dot(d, s->sub_n);
             break;
         }
         if (!(ell < INFINITY)) { res->state = OR_ESCAPED; break; }   /* open line of sight: cannot happen in a closed chamber */
@@ -815,12 +818,13 @@ static void make_tab(const double* prm, const double* theta, const double* betam
 /* ------------------------------------------------------------------------- */
 /* Public driver entry points.                                               */
 /* ------------------------------------------------------------------------- */
-#define OR_REC 8   /* record: x, y, z, state, bin, events, diffusive steps, final E */
+#define OR_REC 9   /* record: x, y, z, state, bin, events, diffusive steps, final E, incidence cosine */
 
 static void write_record(double* rec, const result_t* r)
 {
     rec[0] = r->x[0]; rec[1] = r->x[1]; rec[2] = r->x[2];
     rec[3] = r->state; rec[4] = r->bin; rec[5] = r->events; rec[6] = r->ndiff; rec[7] = r->E;
+    rec[8] = r->cos_in;
 }
 
 /*
