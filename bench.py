@@ -64,7 +64,7 @@ PEAK_ALU = 256 * 128 * 2.4e9
 # HBM bytes per launch of each kernel on the default workload from rocprofv3: FETCH_SIZE x 2.000
 # + WRITE_SIZE x 1.000 (KiB per dispatch; factors from a 1 GiB copy and fill).  Valid for the
 # kernels they were taken on; set to None when a kernel changes.
-TRAFFIC = {"k_diffusive32": (320941 * 2.0 + 37170) * 1024, "k_ballistic32": (1633 * 2.0 + 712945) * 1024}
+TRAFFIC = {}
 
 
 def algorithmic_ops(counters):
@@ -166,6 +166,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=25.0,
                     help="target of the CPU pilot-based sizing (the measured run usually takes about half)")
     ap.add_argument("--launch", default="", help="blocks,threads,refill_min,refill_ballistic instead of autotuning")
+    ap.add_argument("--arrivals", action="store_true",
+                    help="also tally arrival energy and angle histograms and per-bin energy sums")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
@@ -202,7 +204,7 @@ def main():
     else:
         launch = plan.launch if args.no_autotune else plan.autotune()
     tune_s = time.perf_counter() - t
-    bufs = plan.allocate(profiles=True)
+    bufs = plan.allocate(profiles=True, arrivals=args.arrivals)
     wall, ms, phases = time_steps(plan, bufs, args.seed, args.steps, args.warmup)
     counters = bufs["counters"].view(plan.n_segments, spx._native.N_COUNTERS).cpu().numpy().astype(np.float64)
     n_part = float(counters[:, 0].sum())
@@ -237,7 +239,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": desc, "particles_per_step": int(n_part), "segments": plan.n_segments,
-                   "launch": launch, "seed": args.seed},
+                   "launch": launch, "seed": args.seed, "arrival_tallies": bool(args.arrivals)},
         "collisions_per_s": (coll + diff) / (ms_step * 1e-3),
         "ballistic_collisions_per_s": coll / (ms_step * 1e-3),
         "diffusive_steps_per_s": diff / (ms_step * 1e-3),

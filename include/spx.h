@@ -134,7 +134,30 @@ typedef struct spx_record {
     uint32_t bin;                /* iv * nu + iu if DEPOSITED, else 0xFFFFFFFF */
     uint32_t events;             /* flights taken */
     uint32_t diffusive;          /* diffusive steps that ended in the gas */
+    double cos_in;               /* DEPOSITED: cosine of the incidence angle from the substrate
+                                    normal (-d . normal, in (0, 1]); else 0 */
 } spx_record;
+
+/* Arrival tallies of the atoms deposited on the substrate (Introduction: a Monte Carlo model
+ * yields the energy and angular distributions of arriving particles besides the profile).
+ * Energy bin = number of k in 1..59 with E >= 10^(-3 + k/10) eV (so 60 bins, ends open);
+ * angle bin = number of k in 1..89 with cos_in <= cos(k deg) (90 bins of 1 deg of the
+ * incidence angle).  A thermalised atom arrives with the energy it had when it thermalised. */
+#define SPX_ARRIVAL_E_BINS 60
+#define SPX_ARRIVAL_A_BINS 90
+#define SPX_ESUM_SCALE 16777216.0   /* energy sums count units of 2^-24 eV: rint(E * 2^24) */
+
+/* Output buffers of spx_run_ex (device pointers, caller-owned, overwritten).  counts and
+ * counters are required; the others may be NULL (the three arrival outputs together). */
+typedef struct spx_outputs {
+    uint64_t* counts;            /* uint64[n_bins_total] deposits per bin */
+    uint64_t* counters;          /* uint64[n_segments * SPX_N_COUNTERS] */
+    double* profiles;            /* double[n_bins_total] counts / (N_seg * bin area) */
+    spx_record* records;         /* spx_record[n_particles_total] */
+    uint64_t* arrival_energy;    /* uint64[n_segments][SPX_ARRIVAL_E_BINS] deposits per energy bin */
+    uint64_t* arrival_angle;     /* uint64[n_segments][SPX_ARRIVAL_A_BINS] deposits per angle bin */
+    uint64_t* energy_sum;        /* uint64[n_bins_total] sum over the bin's deposits of rint(E * 2^24) */
+} spx_outputs;
 
 typedef struct spx_plan spx_plan;
 
@@ -168,6 +191,16 @@ int spx_plan_layout(const spx_plan* plan, uint64_t* h_bin_off, uint64_t* h_first
  * graph); precision 64 runs one plain FP64 launch per segment.  Asynchronous. */
 int spx_run(spx_plan* plan, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters,
             double* d_profiles, spx_record* d_records, void* stream);
+
+/* spx_run with the outputs in a struct, including the arrival tallies (Introduction:
+ * energy and angular distributions of arriving particles).  Asynchronous on `stream`;
+ * SPX_EINVAL for missing required outputs or a partial set of arrival outputs. */
+int spx_run_ex(spx_plan* plan, uint64_t seed, const spx_outputs* out, void* stream);
+
+/* Bin edges of the arrival tallies as the kernels use them: energy edges [61] (eV) and the
+ * cosines of the angle edges [91], in double (plain FP64 path) and float (batched FP32 path;
+ * the double values rounded).  Any pointer may be NULL. */
+int spx_arrival_edges(double* h_energy_edges, double* h_cos_edges, float* h_energy_edges32, float* h_cos_edges32);
 
 /* Choose launch parameters of the FP32 transport (block size and the two refill
  * thresholds) by timing short runs on `stream`; synchronous; results are unaffected. */

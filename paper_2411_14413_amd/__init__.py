@@ -21,7 +21,7 @@ from ._native import COUNTER_NAMES, DEPOSITED, ESCAPED, N_COUNTERS, WALL, SpxErr
 
 __all__ = ["Plan", "philox", "area_centres", "area_gather", "comp_forward", "comp_backward", "comp_sqdist",
            "CompositionMap", "SquaredDistance", "records_to_numpy", "COUNTER_NAMES", "DEPOSITED", "WALL",
-           "ESCAPED", "SpxError", "version"]
+           "ESCAPED", "SpxError", "version", "arrival_edges"]
 
 
 def _torch():
@@ -132,7 +132,8 @@ class Plan:
             self._h = None
 
     # -- running ---------------------------------------------------------------------------
-    def allocate(self, profiles: bool = True, records: bool = False, device=None) -> Dict[str, object]:
+    def allocate(self, profiles: bool = True, records: bool = False, arrivals: bool = False,
+                 device=None) -> Dict[str, object]:
         torch = _torch()
         dev = device or torch.device("cuda", torch.cuda.current_device())
         out = dict(
@@ -141,18 +142,32 @@ class Plan:
             profiles=torch.empty(self.n_bins, dtype=torch.float64, device=dev) if profiles else None,
             records=torch.empty(self.n_particles * N.RECORD_BYTES, dtype=torch.uint8, device=dev) if records else None,
         )
+        if arrivals:
+            out["arrival_energy"] = torch.empty(self.n_segments * N.ARRIVAL_E_BINS, dtype=torch.int64, device=dev)
+            out["arrival_angle"] = torch.empty(self.n_segments * N.ARRIVAL_A_BINS, dtype=torch.int64, device=dev)
+            out["energy_sum"] = torch.empty(self.n_bins, dtype=torch.int64, device=dev)
         return out
 
     def run_into(self, seed: int, bufs: Dict[str, object], stream=None) -> None:
         """Enqueue one run writing into pre-allocated buffers (see allocate)."""
+        if bufs.get("arrival_energy") is not None:
+            o = N.Outputs(_ptr(bufs["counts"]), _ptr(bufs["counters"]), _ptr(bufs.get("profiles")),
+                          _ptr(bufs.get("records")), _ptr(bufs["arrival_energy"]), _ptr(bufs["arrival_angle"]),
+                          _ptr(bufs["energy_sum"]))
+            check(lib().spx_run_ex(self._h, int(seed) & (2**64 - 1), ctypes.byref(o), _stream(stream)), "spx_run_ex")
+            return
         check(lib().spx_run(self._h, int(seed) & (2**64 - 1), _ptr(bufs["counts"]), _ptr(bufs["counters"]),
                             _ptr(bufs.get("profiles")), _ptr(bufs.get("records")), _stream(stream)), "spx_run")
 
-    def run(self, seed: int = 0, profiles: bool = True, records: bool = False, stream=None) -> Dict[str, object]:
-        bufs = self.allocate(profiles=profiles, records=records)
+    def run(self, seed: int = 0, profiles: bool = True, records: bool = False, arrivals: bool = False,
+            stream=None) -> Dict[str, object]:
+        bufs = self.allocate(profiles=profiles, records=records, arrivals=arrivals)
         self.run_into(seed, bufs, stream)
         out = dict(bufs)
         out["counters"] = bufs["counters"].view(self.n_segments, N_COUNTERS)
+        if arrivals:
+            out["arrival_energy"] = bufs["arrival_energy"].view(self.n_segments, N.ARRIVAL_E_BINS)
+            out["arrival_angle"] = bufs["arrival_angle"].view(self.n_segments, N.ARRIVAL_A_BINS)
         out["counts_seg"] = [bufs["counts"][o:o + nv * nu].view(nv, nu) for o, (nv, nu) in
                              zip(self.bin_off, self.shapes)]
         if profiles:
@@ -201,11 +216,24 @@ class Plan:
 
 
 RECORD_DTYPE = np.dtype([("x", "<f8"), ("y", "<f8"), ("z", "<f8"), ("E", "<f8"), ("state", "<u4"),
-                         ("bin", "<u4"), ("events", "<u4"), ("diffusive", "<u4")])
+                         ("bin", "<u4"), ("events", "<u4"), ("diffusive", "<u4"), ("cos_in", "<f8")])
+
+
+def arrival_edges():
+    """Bin edges of the arrival tallies: (energy [61] f64, cos [91] f64, energy f32, cos f32)."""
+    e64 = np.empty(N.ARRIVAL_E_BINS + 1)
+    c64 = np.empty(N.ARRIVAL_A_BINS + 1)
+    e32 = np.empty(N.ARRIVAL_E_BINS + 1, dtype=np.float32)
+    c32 = np.empty(N.ARRIVAL_A_BINS + 1, dtype=np.float32)
+    fp = ctypes.POINTER(ctypes.c_float)
+    check(lib().spx_arrival_edges(e64.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  c64.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  e32.ctypes.data_as(fp), c32.ctypes.data_as(fp)), "spx_arrival_edges")
+    return e64, c64, e32, c32
 
 
 def records_to_numpy(rec_bytes) -> np.ndarray:
-    """Host structured array (x, y, z, E, state, bin, events, diffusive) from a record buffer."""
+    """Host structured array (x, y, z, E, state, bin, events, diffusive, cos_in) from a record buffer."""
     a = rec_bytes.detach().cpu().numpy() if hasattr(rec_bytes, "detach") else np.asarray(rec_bytes)
     return a.view(RECORD_DTYPE)
 

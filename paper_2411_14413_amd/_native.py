@@ -55,11 +55,20 @@ class Params(ctypes.Structure):
 class Record(ctypes.Structure):
     _fields_ = [("x", ctypes.c_double), ("y", ctypes.c_double), ("z", ctypes.c_double), ("E", ctypes.c_double),
                 ("state", ctypes.c_uint32), ("bin", ctypes.c_uint32), ("events", ctypes.c_uint32),
-                ("diffusive", ctypes.c_uint32)]
+                ("diffusive", ctypes.c_uint32), ("cos_in", ctypes.c_double)]
 
 
 RECORD_BYTES = ctypes.sizeof(Record)
-assert RECORD_BYTES == 48
+assert RECORD_BYTES == 56
+
+ARRIVAL_E_BINS, ARRIVAL_A_BINS = 60, 90
+ESUM_SCALE = 2.0 ** 24
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("counts", ctypes.c_void_p), ("counters", ctypes.c_void_p), ("profiles", ctypes.c_void_p),
+                ("records", ctypes.c_void_p), ("arrival_energy", ctypes.c_void_p), ("arrival_angle", ctypes.c_void_p),
+                ("energy_sum", ctypes.c_void_p)]
 
 # Every entry point of include/spx.h: name -> (restype, argtypes)
 _vp = ctypes.c_void_p
@@ -72,6 +81,9 @@ SIGNATURES = {
                                       ctypes.POINTER(_i32)]),
     "spx_plan_layout": (ctypes.c_int, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "spx_run": (ctypes.c_int, [_vp, _u64, _vp, _vp, _vp, _vp, _vp]),
+    "spx_run_ex": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(Outputs), _vp]),
+    "spx_arrival_edges": (ctypes.c_int, [ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), ctypes.POINTER(ctypes.c_float),
+                                         ctypes.POINTER(ctypes.c_float)]),
     "spx_autotune": (ctypes.c_int, [_vp, _vp]),
     "spx_get_launch": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                       ctypes.POINTER(_i32)]),

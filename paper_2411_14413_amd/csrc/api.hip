@@ -330,7 +330,7 @@ static void release(Plan* P)
     if (P->graph) (void)hipGraphDestroy(P->graph);
     void* ptrs[] = {P->d_theta64, P->d_betamax64, P->d_theta32, P->d_betamax32, P->d_seg32,   P->d_seg64,
                     P->d_tfirst,  P->d_torder,    P->d_qstate,  P->d_queue,     P->d_bin_off, P->d_seg_norm,
-                    P->d_rt32,    P->d_rt64};
+                    P->d_rt32,    P->d_rt64,      P->d_edges32, P->d_edges64};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (hipEvent_t e : P->phase_events) (void)hipEventDestroy(e);
@@ -436,6 +436,20 @@ static int create(const spx_config* cfgs, int n_cfgs, const spx_params* prm, Pla
                                           last ? 0.0 : sg.rt_r[i + 1] - sg.rt_r[i]});
         }
     }
+    {
+        double e[SPX_ARRIVAL_E_BINS + 1 + SPX_ARRIVAL_A_BINS + 1];
+        arrival_edges(e, e + SPX_ARRIVAL_E_BINS + 1);
+        float f[SPX_ARRIVAL_E_BINS + 1 + SPX_ARRIVAL_A_BINS + 1];
+        const size_t ne = sizeof(e) / sizeof(e[0]);
+        for (size_t i = 0; i < ne; ++i) f[i] = (float)e[i];
+        if (dalloc(&P->d_edges32, ne) != SPX_OK || dalloc(&P->d_edges64, ne) != SPX_OK ||
+            hipMemcpy(P->d_edges32, f, sizeof(f), hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(P->d_edges64, e, sizeof(e), hipMemcpyHostToDevice) != hipSuccess) {
+            set_error("copying the arrival bin edges to the device failed");
+            release(P);
+            return SPX_EDEVICE;
+        }
+    }
     if (!rt64.empty()) {
         std::vector<RtNode<float>> rt32;
         for (const auto& q : rt64)
@@ -531,7 +545,7 @@ static int add_phase_events(Plan* P, hipGraph_t g)
         if (ty != hipGraphNodeTypeKernel) continue;
         hipKernelNodeParams kp{};
         SPX_HIP(hipGraphKernelNodeGetParams(chain[i], &kp));
-        if (kp.func != ballistic_kernel() || i == 0) continue;
+        if (!is_ballistic_kernel(kp.func) || i == 0) continue;
         const hipGraphNode_t prev = chain[i - 1], bal = chain[i], dif = chain[i + 1];
         hipGraphNode_t e0, e1, e2;
         SPX_HIP(hipGraphAddEventRecordNode(&e0, g, &prev, 1, P->phase_events[3 * r]));
@@ -549,17 +563,18 @@ static int add_phase_events(Plan* P, hipGraph_t g)
     return SPX_OK;
 }
 
-static int run(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
-               spx_record* d_records, hipStream_t st)
+static int run(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st)
 {
-    if (P->params.precision == 64)
-        return launch_transport64(P, seed, d_counts, d_counters, d_profiles, d_records, st);
+    if (P->params.precision == 64) return launch_transport64(P, seed, o, st);
     GraphKey key;
     key.seed = seed;
-    key.counts = d_counts;
-    key.counters = d_counters;
-    key.profiles = d_profiles;
-    key.records = d_records;
+    key.counts = o.counts;
+    key.counters = o.counters;
+    key.profiles = o.profiles;
+    key.records = o.records;
+    key.arr_E = o.arr_E;
+    key.arr_A = o.arr_A;
+    key.esum = o.esum;
     key.blocks = P->blocks;
     key.threads = P->threads;
     key.refill = P->refill_min;
@@ -574,9 +589,8 @@ static int run(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters,
             P->graph = nullptr;
         }
         SPX_HIP(hipStreamBeginCapture(P->work_stream, hipStreamCaptureModeThreadLocal));
-        const int rc = launch_transport32(P, seed, d_counts, d_counters, d_profiles, d_records, P->work_stream,
-                                          P->d_tfirst, P->n_tickets, P->blocks, P->threads, P->refill_min,
-                                          P->refill_ballistic, nullptr);
+        const int rc = launch_transport32(P, seed, o, P->work_stream, P->d_tfirst, P->n_tickets, P->blocks,
+                                          P->threads, P->refill_min, P->refill_ballistic, nullptr);
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(P->work_stream, &g);
         if (rc != SPX_OK) {
@@ -642,8 +656,10 @@ static int autotune(Plan* P, hipStream_t st)
             float ms_min = 1e30f;
             for (int rep = 0; rep < 2 && rc == SPX_OK; ++rep) {
                 if (hipEventRecord(e0, st) != hipSuccess) rc = SPX_EDEVICE;
-                if (rc == SPX_OK) rc = launch_transport32(P, 0x5eed, d_counts, d_ctr, nullptr, nullptr, st, d_tf, tf[n],
-                                                          blocks, t, ro[0], ro[1], nullptr);
+                Outputs to;
+                to.counts = d_counts;
+                to.counters = d_ctr;
+                if (rc == SPX_OK) rc = launch_transport32(P, 0x5eed, to, st, d_tf, tf[n], blocks, t, ro[0], ro[1], nullptr);
                 if (rc == SPX_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
                     rc = SPX_EDEVICE;
                 float ms = 0.f;
@@ -728,13 +744,56 @@ int spx_run(spx_plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters
 {
     if (!P) return fail("null plan");
     if (!d_counts || !d_counters) return fail("spx_run: d_counts and d_counters are required");
+    Outputs o;
+    o.counts = d_counts;
+    o.counters = d_counters;
+    o.profiles = d_profiles;
+    o.records = d_records;
     try {
         SPX_HIP(hipSetDevice(P->device));
-        return run(P, seed, d_counts, d_counters, d_profiles, d_records, (hipStream_t)stream);
+        return run(P, seed, o, (hipStream_t)stream);
     } catch (const std::exception& e) {
         set_error(std::string("spx_run: ") + e.what());
         return SPX_ENOMEM;
     }
+}
+
+int spx_run_ex(spx_plan* P, uint64_t seed, const spx_outputs* out, void* stream)
+{
+    if (!P || !out) return fail("null argument");
+    if (!out->counts || !out->counters) return fail("spx_run_ex: counts and counters are required");
+    const int na = (out->arrival_energy != nullptr) + (out->arrival_angle != nullptr) + (out->energy_sum != nullptr);
+    if (na != 0 && na != 3) return fail("spx_run_ex: the arrival outputs go together (all three or none)");
+    Outputs o;
+    o.counts = out->counts;
+    o.counters = out->counters;
+    o.profiles = out->profiles;
+    o.records = out->records;
+    o.arr_E = out->arrival_energy;
+    o.arr_A = out->arrival_angle;
+    o.esum = out->energy_sum;
+    try {
+        SPX_HIP(hipSetDevice(P->device));
+        return run(P, seed, o, (hipStream_t)stream);
+    } catch (const std::exception& e) {
+        set_error(std::string("spx_run_ex: ") + e.what());
+        return SPX_ENOMEM;
+    }
+}
+
+int spx_arrival_edges(double* e64, double* c64, float* e32, float* c32)
+{
+    double e[SPX_ARRIVAL_E_BINS + 1], c[SPX_ARRIVAL_A_BINS + 1];
+    arrival_edges(e, c);
+    for (int k = 0; k <= SPX_ARRIVAL_E_BINS; ++k) {
+        if (e64) e64[k] = e[k];
+        if (e32) e32[k] = (float)e[k];
+    }
+    for (int k = 0; k <= SPX_ARRIVAL_A_BINS; ++k) {
+        if (c64) c64[k] = c[k];
+        if (c32) c32[k] = (float)c[k];
+    }
+    return SPX_OK;
 }
 
 int spx_autotune(spx_plan* P, void* stream)

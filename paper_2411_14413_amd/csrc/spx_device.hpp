@@ -504,7 +504,16 @@ template <typename R> struct Particle {
 struct Term {
     int state;         // HIT_DEPOSITED / HIT_WALL / HIT_ESCAPED, HIT_NONE while alive
     int bin;
+    float cos_in;      // deposits: cosine of the incidence angle (-d . substrate normal); else 0
 };
+
+// Terminal outcome of a surface hit along direction d.
+template <typename R>
+__device__ __forceinline__ Term hit_term(const SegDev<R>& s, int state, R qu, R qv, const R* d)
+{
+    if (state != HIT_DEPOSITED) return Term{state, -1, 0.f};
+    return Term{state, tally_bin(s, qu, qv), (float)(-dot3(d, s.sub_n))};
+}
 
 // One flight of a live particle in state MODE (ST_BALLISTIC or ST_DIFFUSIVE): event
 // number p.e + 1.  Returns the terminal outcome (HIT_NONE if still in the gas).
@@ -512,7 +521,7 @@ template <typename R, int MODE>
 __device__ __forceinline__ Term step_mode(const SegDev<R>& s, const TabDev<R>& tb, uint32_t k0, uint32_t k1,
                                           uint32_t pid, uint32_t cap, Particle<R>& p)
 {
-    if (p.e >= cap) return Term{HIT_ESCAPED, -1};
+    if (p.e >= cap) return Term{HIT_ESCAPED, -1, 0.f};
     const uint32_t e = p.e + 1;
     p.e = e;
     uint4 r = make_uint4(0u, 0u, 0u, 0u);
@@ -530,9 +539,9 @@ __device__ __forceinline__ Term step_mode(const SegDev<R>& s, const TabDev<R>& t
     if (h.state != HIT_NONE) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) kahan_add(p.x[i], p.xc[i], t * p.d[i]);
-        return Term{h.state, h.state == HIT_DEPOSITED ? tally_bin(s, qu, qv) : -1};
+        return hit_term(s, h.state, qu, qv, p.d);
     }
-    if (!(ell < m_inf<R>())) return Term{HIT_ESCAPED, -1};
+    if (!(ell < m_inf<R>())) return Term{HIT_ESCAPED, -1, 0.f};
 #pragma unroll
     for (int i = 0; i < 3; ++i) kahan_add(p.x[i], p.xc[i], ell * p.d[i]);
     if (MODE == ST_BALLISTIC) {
@@ -545,12 +554,12 @@ __device__ __forceinline__ Term step_mode(const SegDev<R>& s, const TabDev<R>& t
             p.r2 = (R)-1;      // no clearance ball yet: the first diffusive step is tested
         }
         if (!(m_finite(p.x[0]) && m_finite(p.x[1]) && m_finite(p.x[2]) && m_finite(p.E)))
-            return Term{HIT_ESCAPED, -1};
+            return Term{HIT_ESCAPED, -1, 0.f};
     } else {
         // an isotropic unit direction and a finite step keep the position finite
         ++p.ndiff;
     }
-    return Term{HIT_NONE, -1};
+    return Term{HIT_NONE, -1, 0.f};
 }
 
 // The diffusive move split so that two walks can share it bit for bit: the step vector
@@ -603,7 +612,7 @@ constexpr float CLEAR_MARGIN = 0.02f;
 __device__ __forceinline__ Term step_diffusive_ball(const SegDev<float>& s, uint32_t k0, uint32_t k1, uint32_t pid,
                                                     uint32_t cap, Particle<float>& p)
 {
-    if (p.e >= cap) return Term{HIT_ESCAPED, -1};
+    if (p.e >= cap) return Term{HIT_ESCAPED, -1, 0.f};
     const uint32_t e = p.e + 1;
     p.e = e;
     uint32_t k[3];
@@ -621,9 +630,9 @@ __device__ __forceinline__ Term step_diffusive_ball(const SegDev<float>& s, uint
         if (h.state != HIT_NONE) {
 #pragma unroll
             for (int i = 0; i < 3; ++i) kahan_add(p.x[i], p.xc[i], th * dir[i]);
-            return Term{h.state, h.state == HIT_DEPOSITED ? tally_bin(s, qu, qv) : -1};
+            return hit_term(s, h.state, qu, qv, dir);
         }
-        if (!(ell < m_inf<float>())) return Term{HIT_ESCAPED, -1};
+        if (!(ell < m_inf<float>())) return Term{HIT_ESCAPED, -1, 0.f};
     }
     kahan_commit(p.x, p.xc, y, t);
     ++p.ndiff;
@@ -632,7 +641,7 @@ __device__ __forceinline__ Term step_diffusive_ball(const SegDev<float>& s, uint
         p.d[0] = p.x[0]; p.d[1] = p.x[1]; p.d[2] = p.x[2];
         p.r2 = c > 0.f ? c * c : -1.f;
     }
-    return Term{HIT_NONE, -1};
+    return Term{HIT_NONE, -1, 0.f};
 }
 
 // The two halves of step_diffusive_ball for a wave that defers its surface tests.
@@ -674,13 +683,13 @@ __device__ __forceinline__ void diffusive_substep(const SegDev<float>& s, uint4 
 __device__ __forceinline__ Term diffusive_advance(const SegDev<float>& s, uint32_t k0, uint32_t k1, uint32_t pid,
                                                   uint32_t cap, Particle<float>& p, bool& held)
 {
-    if (p.e >= cap) return Term{HIT_ESCAPED, -1};
+    if (p.e >= cap) return Term{HIT_ESCAPED, -1, 0.f};
     const uint4 w = diffusive_block(pid, p.e + 1, s.cfgcat, k0, k1);
     // the even step of the block (if the next event is even), then its odd step unless the
     // even one is held or the cap is reached (a capped history escapes at its next step)
     diffusive_substep(s, w, false, ((p.e + 1) & 1u) == 0, p, held);
     diffusive_substep(s, w, true, !held && p.e < cap, p, held);
-    return Term{HIT_NONE, -1};
+    return Term{HIT_NONE, -1, 0.f};
 }
 
 __device__ __forceinline__ Term diffusive_resolve(const SegDev<float>& s, Particle<float>& p)
@@ -692,9 +701,9 @@ __device__ __forceinline__ Term diffusive_resolve(const SegDev<float>& s, Partic
     if (h.state != HIT_NONE) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) kahan_add(p.x[i], p.xc[i], th * dir[i]);
-        return Term{h.state, h.state == HIT_DEPOSITED ? tally_bin(s, qu, qv) : -1};
+        return hit_term(s, h.state, qu, qv, dir);
     }
-    if (!(ell < m_inf<float>())) return Term{HIT_ESCAPED, -1};
+    if (!(ell < m_inf<float>())) return Term{HIT_ESCAPED, -1, 0.f};
     float v[3], y[3], t[3];
     step_vector(ell, dir, v);
     kahan_try(p.x, p.xc, v, y, t);
@@ -703,7 +712,7 @@ __device__ __forceinline__ Term diffusive_resolve(const SegDev<float>& s, Partic
     const float c = clearance(s, p.x) - CLEAR_MARGIN;
     p.d[0] = p.x[0]; p.d[1] = p.x[1]; p.d[2] = p.x[2];
     p.r2 = c > 0.f ? c * c : -1.f;
-    return Term{HIT_NONE, -1};
+    return Term{HIT_NONE, -1, 0.f};
 }
 
 // Diffusive steps of the thermalised particle of lane L taken with the whole wave: lane j
@@ -779,5 +788,29 @@ __device__ __forceinline__ void start(const SegDev<R>& s, uint32_t k0, uint32_t 
     p.ncoll = 0;
     p.st = ST_BALLISTIC;
 }
+
+// Arrival tallies of deposits.  Energy bin = #{k in 1..59 : E >= e_k} with e_k = 10^(-3+k/10)
+// eV; angle bin = #{k in 1..89 : cos_in <= cos(k deg)}: comparisons with tabulated edges, so
+// a bin is decided exactly as a host-side histogram of the records with the same edges would.
+template <typename R> __device__ __forceinline__ int energy_bin(const R* e, R E)
+{
+    int lo = 0, hi = 59;                 // largest j with j == 0 or e[j] <= E
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (e[mid] <= E) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+template <typename R> __device__ __forceinline__ int angle_bin(const R* c, R cos_in)
+{
+    int lo = 0, hi = 89;                 // largest j with j == 0 or cos_in <= c[j]
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (cos_in <= c[mid]) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+// Energy in integer units of 2^-24 eV (exact sums in any order).
+__device__ __forceinline__ unsigned long long energy_units(double E) { return (unsigned long long)rint(E * 0x1p24); }
 
 }  // namespace spx

@@ -73,6 +73,11 @@ struct TransportArgs {
     unsigned long long* counts;
     unsigned long long* counters;
     spx_record* records;
+    unsigned long long* arr_E;  // arrival energy histograms [n_seg][SPX_ARRIVAL_E_BINS] (nullable)
+    unsigned long long* arr_A;  // arrival angle histograms [n_seg][SPX_ARRIVAL_A_BINS] (nullable with arr_E)
+    unsigned long long* esum;   // per tally bin: arrival energies in units of 2^-24 eV (nullable with arr_E)
+    const float* e_edges;       // [SPX_ARRIVAL_E_BINS + 1] energy edges, eV
+    const float* c_edges;       // [SPX_ARRIVAL_A_BINS + 1] cos(k deg)
     uint64_t tbase;             // first ticket of the round
     uint64_t total;             // tickets of the round
     uint32_t k0, k1;            // Philox key (seed words)
@@ -83,6 +88,18 @@ struct TransportArgs {
     uint32_t n_bins;            // tally bins of the plan
     int32_t lds_counters;       // per-segment counters privatised in LDS
     int32_t lds_tally;          // whole tally privatised in LDS (u32 per bin)
+    int32_t lds_arrivals;       // arrival histograms privatised in LDS (u32)
+};
+
+// Output buffers of one run (device pointers; all but counts and counters nullable).
+struct Outputs {
+    uint64_t* counts = nullptr;
+    uint64_t* counters = nullptr;
+    double* profiles = nullptr;
+    spx_record* records = nullptr;
+    uint64_t* arr_E = nullptr;
+    uint64_t* arr_A = nullptr;
+    uint64_t* esum = nullptr;
 };
 
 constexpr uint64_t ROUND_MAX = 1ull << 25;   // tickets per round: a 1.6 GB queue of thermalised atoms
@@ -94,6 +111,7 @@ constexpr uint64_t TICKET_CHUNK = 64;        // tickets a wave claims per global
 constexpr int DEFER_MIN = 8;                  // held diffusive steps that trigger a wave's surface tests
 constexpr int COOP_MAX = 8;                   // drained waves with at most this many live lanes walk cooperatively
 constexpr size_t LDS_TALLY_MAX = 49152;      // bytes: up to 12288 bins
+constexpr size_t LDS_ARRIVALS_MAX = 4096;     // bytes: arrival histograms of up to 6 segments
 
 struct GraphKey {
     uint64_t seed = 0;
@@ -101,11 +119,14 @@ struct GraphKey {
     void* counters = nullptr;
     void* profiles = nullptr;
     void* records = nullptr;
+    void* arr_E = nullptr;
+    void* arr_A = nullptr;
+    void* esum = nullptr;
     int blocks = 0, threads = 0, refill = 0, refill_b = 0;
     bool operator==(const GraphKey& o) const
     {
         return seed == o.seed && counts == o.counts && counters == o.counters && profiles == o.profiles &&
-               records == o.records && blocks == o.blocks && threads == o.threads && refill == o.refill &&
+               records == o.records && arr_E == o.arr_E && arr_A == o.arr_A && esum == o.esum && blocks == o.blocks && threads == o.threads && refill == o.refill &&
                refill_b == o.refill_b;
     }
 };
@@ -129,6 +150,8 @@ struct spx_plan {
     float* d_betamax32 = nullptr;
     spx::SegDev<float>* d_seg32 = nullptr;
     spx::SegDev<double>* d_seg64 = nullptr;
+    float* d_edges32 = nullptr;               // arrival bin edges: energy [61] then cos [91]
+    double* d_edges64 = nullptr;
     spx::RtNode<float>* d_rt32 = nullptr;     // measured racetracks of all segments
     spx::RtNode<double>* d_rt64 = nullptr;
     uint64_t* d_tfirst = nullptr;
@@ -154,13 +177,13 @@ using Plan = spx_plan;
 int build_tables(Plan* P);
 // events (nullable, not while capturing): 3 per round, recorded at the round's start, after
 // its ballistic phase and after its diffusive phase.
-int launch_transport32(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
-                       spx_record* d_records, hipStream_t st, const uint64_t* tfirst, uint64_t total,
-                       int blocks, int threads, int refill_min, int refill_ballistic, const hipEvent_t* events);
+int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st, const uint64_t* tfirst,
+                       uint64_t total, int blocks, int threads, int refill_min, int refill_ballistic,
+                       const hipEvent_t* events);
 uint64_t rounds_of(uint64_t total);
-const void* ballistic_kernel();
-const void* diffusive_kernel();
-int launch_transport64(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
-                       spx_record* d_records, hipStream_t st);
+bool is_ballistic_kernel(const void* f);
+int launch_transport64(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st);
+// Arrival bin edges in double (as the comparator uses them); the batched path rounds them to float.
+void arrival_edges(double* e_edges, double* c_edges);
 int occupancy_transport32(const Plan* P, int threads, int* blocks_per_cu);   // the smaller of the two kernels
 }  // namespace spx

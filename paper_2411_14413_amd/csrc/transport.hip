@@ -18,6 +18,8 @@
 // one launch per segment.  It is the comparator for the batched path.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "spx_host.hpp"
 
 namespace spx {
@@ -42,6 +44,7 @@ __device__ __forceinline__ void write_record(spx_record* rec, const SegDev<R>& s
     r.bin = t.state == HIT_DEPOSITED ? (uint32_t)t.bin : 0xFFFFFFFFu;
     r.events = p.e;
     r.diffusive = p.ndiff;
+    r.cos_in = (double)t.cos_in;
     rec[s.first_rec + pid] = r;
 }
 
@@ -55,7 +58,27 @@ struct LaneAcc {
 struct BlockTally {
     unsigned long long* lcnt;   // LDS per-segment counters (valid if a.lds_counters)
     uint32_t* ltally;           // LDS tally (valid if a.lds_tally)
+    uint32_t* larr;             // LDS arrival histograms [n_seg][E bins + A bins] (valid if a.lds_arrivals)
 };
+
+constexpr int ARR_BINS = SPX_ARRIVAL_E_BINS + SPX_ARRIVAL_A_BINS;
+
+// Arrival tallies of one deposit: energy and angle histograms of its segment, energy sum of
+// its tally bin.
+__device__ __forceinline__ void tally_arrival(const TransportArgs& a, const BlockTally& bt, int seg, uint64_t bin,
+                                              double E, double cos_in)
+{
+    const int be = energy_bin(a.e_edges, (float)E);
+    const int ba = angle_bin(a.c_edges, (float)cos_in);
+    if (a.lds_arrivals) {
+        atomicAdd(&bt.larr[seg * ARR_BINS + be], 1u);
+        atomicAdd(&bt.larr[seg * ARR_BINS + SPX_ARRIVAL_E_BINS + ba], 1u);
+    } else {
+        atomicAdd(&a.arr_E[(size_t)seg * SPX_ARRIVAL_E_BINS + be], 1ull);
+        atomicAdd(&a.arr_A[(size_t)seg * SPX_ARRIVAL_A_BINS + ba], 1ull);
+    }
+    atomicAdd(&a.esum[bin], energy_units(E));
+}
 
 __device__ __forceinline__ void flush_acc(const TransportArgs& a, const BlockTally& bt, LaneAcc& acc)
 {
@@ -72,6 +95,7 @@ __device__ __forceinline__ void flush_acc(const TransportArgs& a, const BlockTal
 }
 
 // End of a history: counters, tally, optional record; the lane becomes free.
+template <bool ARR>
 __device__ __forceinline__ void terminate(const TransportArgs& a, const BlockTally& bt, const SegDev<float>& s,
                                           uint32_t pid, Particle<float>& p, const Term& t, LaneAcc& acc)
 {
@@ -86,6 +110,7 @@ __device__ __forceinline__ void terminate(const TransportArgs& a, const BlockTal
         const uint64_t b = s.bin_off + (uint64_t)t.bin;
         if (a.lds_tally) atomicAdd(&bt.ltally[b], 1u);
         else atomicAdd(&a.counts[b], 1ull);
+        if (ARR) tally_arrival(a, bt, acc.seg, b, (double)p.E, (double)t.cos_in);
     }
     if (a.records) write_record(a.records, s, pid, p, t);
     p.st = ST_DEAD;
@@ -127,10 +152,13 @@ __device__ __forceinline__ void lds_setup(const TransportArgs& a, BlockTally& bt
 {
     bt.lcnt = lds;
     bt.ltally = (uint32_t*)(lds + (a.lds_counters ? (size_t)a.n_seg * N_COUNTERS : 0));
+    bt.larr = bt.ltally + (a.lds_tally ? a.n_bins : 0u);
     if (a.lds_counters)
         for (int i = threadIdx.x; i < a.n_seg * N_COUNTERS; i += blockDim.x) bt.lcnt[i] = 0;
     if (a.lds_tally)
         for (uint32_t i = threadIdx.x; i < a.n_bins; i += blockDim.x) bt.ltally[i] = 0;
+    if (a.lds_arrivals)
+        for (int i = threadIdx.x; i < a.n_seg * ARR_BINS; i += blockDim.x) bt.larr[i] = 0;
     __syncthreads();
 }
 
@@ -144,6 +172,15 @@ __device__ __forceinline__ void lds_flush(const TransportArgs& a, const BlockTal
     if (a.lds_tally)
         for (uint32_t i = threadIdx.x; i < a.n_bins; i += blockDim.x)
             if (bt.ltally[i]) atomicAdd(&a.counts[i], (unsigned long long)bt.ltally[i]);
+    if (a.lds_arrivals)
+        for (int i = threadIdx.x; i < a.n_seg * ARR_BINS; i += blockDim.x)
+            if (bt.larr[i]) {
+                const int k = i / ARR_BINS, j = i % ARR_BINS;
+                unsigned long long* dst = j < SPX_ARRIVAL_E_BINS
+                                              ? &a.arr_E[(size_t)k * SPX_ARRIVAL_E_BINS + j]
+                                              : &a.arr_A[(size_t)k * SPX_ARRIVAL_A_BINS + (j - SPX_ARRIVAL_E_BINS)];
+                atomicAdd(dst, (unsigned long long)bt.larr[i]);
+            }
 }
 
 // Wave-private run of queue slots [q, q_end), reserved QUEUE_CHUNK at a time with one
@@ -202,6 +239,7 @@ __device__ __forceinline__ void close_run(const TransportArgs& a, const QRun& Q,
 
 // Ballistic flights of the lanes in segment S (uniform: its constants stay in scalar
 // registers) until the wave should refill or has no ballistic lane left.
+template <bool ARR>
 __device__ __forceinline__ void ballistic_loop(const TransportArgs& a, const BlockTally& bt, const SegDev<float>& S,
                                                uint32_t pid, int seg, Particle<float>& p, LaneAcc& acc, QRun& Q,
                                                bool drained, int lane, uint64_t lt_mask)
@@ -209,7 +247,7 @@ __device__ __forceinline__ void ballistic_loop(const TransportArgs& a, const Blo
     for (;;) {
         if (p.st == ST_BALLISTIC) {
             const Term t = step_mode<float, ST_BALLISTIC>(S, a.tab, a.k0, a.k1, pid, a.cap, p);
-            if (t.state != HIT_NONE) terminate(a, bt, S, pid, p, t, acc);
+            if (t.state != HIT_NONE) terminate<ARR>(a, bt, S, pid, p, t, acc);
         }
         hand_over(a, pid, seg, p, acc, Q, lane, lt_mask);
         if (__ballot(p.st == ST_BALLISTIC) == 0) break;
@@ -222,6 +260,7 @@ __device__ __forceinline__ void ballistic_loop(const TransportArgs& a, const Blo
 // hold one (or every diffusive lane does, or the loop is about to end); then the held
 // steps are tested together, so the long test runs in few iterations.  No step is held
 // when the loop returns.
+template <bool ARR>
 __device__ __forceinline__ void diffusive_loop(const TransportArgs& a, const BlockTally& bt, const SegDev<float>& S,
                                                uint32_t pid, Particle<float>& p, LaneAcc& acc, bool drained)
 {
@@ -229,7 +268,7 @@ __device__ __forceinline__ void diffusive_loop(const TransportArgs& a, const Blo
     for (;;) {
         if (p.st == ST_DIFFUSIVE && !held) {
             const Term t = diffusive_advance(S, a.k0, a.k1, pid, a.cap, p, held);
-            if (t.state != HIT_NONE) terminate(a, bt, S, pid, p, t, acc);
+            if (t.state != HIT_NONE) terminate<ARR>(a, bt, S, pid, p, t, acc);
         }
         const uint64_t H = __ballot(held);
         const uint64_t M = __ballot(p.st == ST_DIFFUSIVE);
@@ -239,7 +278,7 @@ __device__ __forceinline__ void diffusive_loop(const TransportArgs& a, const Blo
             if (held) {
                 held = false;
                 const Term t = diffusive_resolve(S, p);
-                if (t.state != HIT_NONE) terminate(a, bt, S, pid, p, t, acc);
+                if (t.state != HIT_NONE) terminate<ARR>(a, bt, S, pid, p, t, acc);
             }
             const uint64_t M2 = __ballot(p.st == ST_DIFFUSIVE);
             stop = M2 == 0 || (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) ||
@@ -254,6 +293,7 @@ __device__ __forceinline__ void diffusive_loop(const TransportArgs& a, const Blo
 // Dynamic LDS: per-segment counters (u64, when lds_counters) then the tally (u32, when lds_tally).
 // At most 96 VGPRs: five waves per SIMD hide the latency of the transcendental and
 // integer-multiply chains.
+template <bool ARR>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5)))
 k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
 {
@@ -300,13 +340,13 @@ k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
         }
         const int s0 = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)B) - 1);
         if (__ballot(p.st == ST_BALLISTIC && seg != s0) == 0) {
-            ballistic_loop(a, bt, segs[s0], pid, s0, p, acc, Q, T.drained, lane, lt_mask);
+            ballistic_loop<ARR>(a, bt, segs[s0], pid, s0, p, acc, Q, T.drained, lane, lt_mask);
         } else {
             // lanes of several segments: one flight with per-lane constants
             if (p.st == ST_BALLISTIC) {
                 const SegDev<float>& s = segs[seg];
                 const Term t = step_mode<float, ST_BALLISTIC>(s, a.tab, a.k0, a.k1, pid, a.cap, p);
-                if (t.state != HIT_NONE) terminate(a, bt, s, pid, p, t, acc);
+                if (t.state != HIT_NONE) terminate<ARR>(a, bt, s, pid, p, t, acc);
             }
             hand_over(a, pid, seg, p, acc, Q, lane, lt_mask);
         }
@@ -316,6 +356,7 @@ k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
 }
 
 // Diffusive phase of one round: the walks of the atoms queued by the ballistic phase.
+template <bool ARR>
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5)))
 k_diffusive32(TransportArgs a, const SegDev<float>* __restrict__ segs)
 {
@@ -375,22 +416,31 @@ k_diffusive32(TransportArgs a, const SegDev<float>* __restrict__ segs)
         }
         const int s0 = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)D) - 1);
         if (__ballot(p.st == ST_DIFFUSIVE && seg != s0) == 0) {
-            diffusive_loop(a, bt, segs[s0], pid, p, acc, T.drained);
+            diffusive_loop<ARR>(a, bt, segs[s0], pid, p, acc, T.drained);
         } else if (p.st == ST_DIFFUSIVE) {
             // lanes of several segments: one step with per-lane constants
             const SegDev<float>& s = segs[seg];
             const Term t = step_diffusive_ball(s, a.k0, a.k1, pid, a.cap, p);
-            if (t.state != HIT_NONE) terminate(a, bt, s, pid, p, t, acc);
+            if (t.state != HIT_NONE) terminate<ARR>(a, bt, s, pid, p, t, acc);
         }
     }
     lds_flush(a, bt, acc);
 }
 
+// Arrival outputs of the comparator (nullable as a group) with its FP64 bin edges.
+struct Arrivals64 {
+    unsigned long long* E;      // this segment's energy histogram
+    unsigned long long* A;      // this segment's angle histogram
+    unsigned long long* esum;   // per tally bin of the plan
+    const double* e_edges;
+    const double* c_edges;
+};
+
 __global__ void __launch_bounds__(256) k_transport64(const SegDev<double>* __restrict__ segp, TabDev<double> tab,
                                                      uint32_t k0, uint32_t k1, uint32_t cap,
                                                      unsigned long long* __restrict__ counts,
                                                      unsigned long long* __restrict__ counters,
-                                                     spx_record* __restrict__ records)
+                                                     spx_record* __restrict__ records, Arrivals64 arr)
 {
     const SegDev<double>& s = *segp;
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -408,7 +458,15 @@ __global__ void __launch_bounds__(256) k_transport64(const SegDev<double>* __res
         acc[C_COLLISIONS] = p.ncoll;
         acc[C_DIFFUSIVE] = p.ndiff;
         acc[C_THERMALIZED] = (p.st == ST_DIFFUSIVE) ? 1u : 0u;
-        if (t.state == HIT_DEPOSITED) atomicAdd(&counts[s.bin_off + (uint64_t)t.bin], 1ull);
+        if (t.state == HIT_DEPOSITED) {
+            const uint64_t b = s.bin_off + (uint64_t)t.bin;
+            atomicAdd(&counts[b], 1ull);
+            if (arr.E) {
+                atomicAdd(&arr.E[energy_bin(arr.e_edges, p.E)], 1ull);
+                atomicAdd(&arr.A[angle_bin(arr.c_edges, (double)t.cos_in)], 1ull);
+                atomicAdd(&arr.esum[b], energy_units(p.E));
+            }
+        }
         if (records) write_record(records, s, pid, p, t);
     }
     // wave sum of the counters, one atomic per counter and wave
@@ -451,13 +509,25 @@ __global__ void k_normalize(const unsigned long long* __restrict__ counts, const
     }
 }
 
-static int launch_zero(Plan* P, uint64_t* d_counts, uint64_t* d_counters, hipStream_t st)
+static int zero_u64(uint64_t* p, uint64_t n, hipStream_t st)
 {
-    const uint64_t n = P->n_bins_total;
+    if (!p || n == 0) return SPX_OK;
     const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 + 1 : 4096);
-    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, (unsigned long long*)d_counts, n,
-                       (unsigned long long*)d_counters, (uint64_t)P->n_seg * N_COUNTERS);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, (unsigned long long*)p, n, (unsigned long long*)nullptr,
+                       (uint64_t)0);
     SPX_HIP(hipGetLastError());
+    return SPX_OK;
+}
+
+static int launch_zero(Plan* P, const Outputs& o, hipStream_t st)
+{
+    SPX_TRY(zero_u64(o.counts, P->n_bins_total, st));
+    SPX_TRY(zero_u64(o.counters, (uint64_t)P->n_seg * N_COUNTERS, st));
+    if (o.arr_E) {
+        SPX_TRY(zero_u64(o.arr_E, (uint64_t)P->n_seg * SPX_ARRIVAL_E_BINS, st));
+        SPX_TRY(zero_u64(o.arr_A, (uint64_t)P->n_seg * SPX_ARRIVAL_A_BINS, st));
+        SPX_TRY(zero_u64(o.esum, P->n_bins_total, st));
+    }
     return SPX_OK;
 }
 
@@ -471,39 +541,44 @@ static int launch_normalize(Plan* P, const uint64_t* d_counts, double* d_profile
     return SPX_OK;
 }
 
-// Dynamic LDS of the FP32 transport for a plan: counters if they fit, tally if it fits.
-size_t transport32_lds(const Plan* P, bool* lds_counters, bool* lds_tally)
+// Dynamic LDS of the FP32 transport for a plan: counters if they fit, tally if it fits, arrival
+// histograms (when requested) if they fit.
+size_t transport32_lds(const Plan* P, bool arrivals, bool* lds_counters, bool* lds_tally, bool* lds_arrivals)
 {
     const size_t cbytes = (size_t)P->n_seg * N_COUNTERS * sizeof(unsigned long long);
     const size_t tbytes = (size_t)P->n_bins_total * sizeof(uint32_t);
+    const size_t abytes = (size_t)P->n_seg * ARR_BINS * sizeof(uint32_t);
     *lds_counters = cbytes <= LDS_COUNTERS_MAX;
     *lds_tally = tbytes <= LDS_TALLY_MAX;
-    return (*lds_counters ? cbytes : 0) + (*lds_tally ? tbytes : 0);
+    *lds_arrivals = arrivals && abytes <= LDS_ARRIVALS_MAX;
+    return (*lds_counters ? cbytes : 0) + (*lds_tally ? tbytes : 0) + (*lds_arrivals ? abytes : 0);
 }
 
 int occupancy_transport32(const Plan* P, int threads, int* blocks_per_cu)
 {
-    bool lc, lt;
-    const size_t smem = transport32_lds(P, &lc, &lt);
+    bool lc, lt, la;
+    const size_t smem = transport32_lds(P, false, &lc, &lt, &la);
     int b1 = 0, b2 = 0;
-    SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_ballistic32, threads, smem));
-    SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_diffusive32, threads, smem));
+    SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_ballistic32<false>, threads, smem));
+    SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_diffusive32<false>, threads, smem));
     *blocks_per_cu = b1 < b2 ? b1 : b2;
     return SPX_OK;
 }
 
 // The batched kernels' entry points, to find their nodes in a captured graph.
-const void* ballistic_kernel() { return (const void*)k_ballistic32; }
-const void* diffusive_kernel() { return (const void*)k_diffusive32; }
+bool is_ballistic_kernel(const void* f)
+{
+    return f == (const void*)k_ballistic32<false> || f == (const void*)k_ballistic32<true>;
+}
 
 // Rounds of a ticket space of `total` tickets: as few as ROUND_MAX allows, of equal size.
 uint64_t rounds_of(uint64_t total) { return total == 0 ? 0 : (total + ROUND_MAX - 1) / ROUND_MAX; }
 
-int launch_transport32(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
-                       spx_record* d_records, hipStream_t st, const uint64_t* tfirst, uint64_t total, int blocks,
-                       int threads, int refill_min, int refill_ballistic, const hipEvent_t* events)
+int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st, const uint64_t* tfirst,
+                       uint64_t total, int blocks, int threads, int refill_min, int refill_ballistic,
+                       const hipEvent_t* events)
 {
-    SPX_TRY(launch_zero(P, d_counts, d_counters, st));
+    SPX_TRY(launch_zero(P, o, st));
     TransportArgs a;
     a.segs = P->d_seg32;
     a.tab.theta = P->d_theta32;
@@ -515,9 +590,14 @@ int launch_transport32(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_c
     a.torder = P->d_torder;
     a.queue = P->d_queue;
     a.qstate = P->d_qstate;
-    a.counts = (unsigned long long*)d_counts;
-    a.counters = (unsigned long long*)d_counters;
-    a.records = d_records;
+    a.counts = (unsigned long long*)o.counts;
+    a.counters = (unsigned long long*)o.counters;
+    a.records = o.records;
+    a.arr_E = (unsigned long long*)o.arr_E;
+    a.arr_A = (unsigned long long*)o.arr_A;
+    a.esum = (unsigned long long*)o.esum;
+    a.e_edges = P->d_edges32;
+    a.c_edges = P->d_edges32 + SPX_ARRIVAL_E_BINS + 1;
     a.k0 = (uint32_t)seed;
     a.k1 = (uint32_t)(seed >> 32);
     a.cap = P->params.event_cap;
@@ -525,10 +605,11 @@ int launch_transport32(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_c
     a.refill_min = refill_min;
     a.refill_ballistic = refill_ballistic;
     a.n_bins = (uint32_t)P->n_bins_total;
-    bool lc, lt;
-    const size_t smem = transport32_lds(P, &lc, &lt);
+    bool lc, lt, la;
+    const size_t smem = transport32_lds(P, o.arr_E != nullptr, &lc, &lt, &la);
     a.lds_counters = lc ? 1 : 0;
     a.lds_tally = lt ? 1 : 0;
+    a.lds_arrivals = la ? 1 : 0;
     const uint64_t n_rounds = rounds_of(total);
     const uint64_t per_round = n_rounds ? (total + n_rounds - 1) / n_rounds : 0;
     // every queue slot a round can reserve: its atoms plus at most one unused run per wave
@@ -543,21 +624,26 @@ int launch_transport32(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_c
         if (events) SPX_HIP(hipEventRecord(events[3 * r], st));
         hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(64), 0, st, P->d_qstate);
         SPX_HIP(hipGetLastError());
-        hipLaunchKernelGGL(k_ballistic32, dim3(blocks), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
+        if (a.arr_E)
+            hipLaunchKernelGGL(k_ballistic32<true>, dim3(blocks), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
+        else
+            hipLaunchKernelGGL(k_ballistic32<false>, dim3(blocks), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
         SPX_HIP(hipGetLastError());
         if (events) SPX_HIP(hipEventRecord(events[3 * r + 1], st));
-        hipLaunchKernelGGL(k_diffusive32, dim3(blocks), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
+        if (a.arr_E)
+            hipLaunchKernelGGL(k_diffusive32<true>, dim3(blocks), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
+        else
+            hipLaunchKernelGGL(k_diffusive32<false>, dim3(blocks), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
         SPX_HIP(hipGetLastError());
         if (events) SPX_HIP(hipEventRecord(events[3 * r + 2], st));
     }
-    if (d_profiles) SPX_TRY(launch_normalize(P, d_counts, d_profiles, st));
+    if (o.profiles) SPX_TRY(launch_normalize(P, o.counts, o.profiles, st));
     return SPX_OK;
 }
 
-int launch_transport64(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters, double* d_profiles,
-                       spx_record* d_records, hipStream_t st)
+int launch_transport64(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st)
 {
-    SPX_TRY(launch_zero(P, d_counts, d_counters, st));
+    SPX_TRY(launch_zero(P, o, st));
     TabDev<double> tab;
     tab.theta = P->d_theta64;
     tab.betamax = P->d_betamax64;
@@ -568,14 +654,26 @@ int launch_transport64(Plan* P, uint64_t seed, uint64_t* d_counts, uint64_t* d_c
         const uint64_t N = P->seg[k].N;
         if (N == 0) continue;
         const uint64_t blocks = (N + 255) / 256;
+        Arrivals64 arr{nullptr, nullptr, nullptr, P->d_edges64, P->d_edges64 + SPX_ARRIVAL_E_BINS + 1};
+        if (o.arr_E) {
+            arr.E = (unsigned long long*)(o.arr_E + (size_t)k * SPX_ARRIVAL_E_BINS);
+            arr.A = (unsigned long long*)(o.arr_A + (size_t)k * SPX_ARRIVAL_A_BINS);
+            arr.esum = (unsigned long long*)o.esum;
+        }
         hipLaunchKernelGGL(k_transport64, dim3((unsigned)blocks), dim3(256), 0, st, P->d_seg64 + k, tab,
                            (uint32_t)seed, (uint32_t)(seed >> 32), P->params.event_cap,
-                           (unsigned long long*)d_counts, (unsigned long long*)(d_counters + (size_t)k * N_COUNTERS),
-                           d_records);
+                           (unsigned long long*)o.counts, (unsigned long long*)(o.counters + (size_t)k * N_COUNTERS),
+                           o.records, arr);
         SPX_HIP(hipGetLastError());
     }
-    if (d_profiles) SPX_TRY(launch_normalize(P, d_counts, d_profiles, st));
+    if (o.profiles) SPX_TRY(launch_normalize(P, o.counts, o.profiles, st));
     return SPX_OK;
+}
+
+void arrival_edges(double* e_edges, double* c_edges)
+{
+    for (int k = 0; k <= SPX_ARRIVAL_E_BINS; ++k) e_edges[k] = std::pow(10.0, -3.0 + k / 10.0);
+    for (int k = 0; k <= SPX_ARRIVAL_A_BINS; ++k) c_edges[k] = std::cos(k * 3.14159265358979323846 / 180.0);
 }
 
 }  // namespace spx

@@ -30,7 +30,8 @@ def test_library_exports_every_declared_symbol():
 
 def test_header_struct_sizes_match_binding():
     from paper_2411_14413_amd import _native as N
-    assert ctypes.sizeof(N.Record) == 48
+    assert ctypes.sizeof(N.Record) == 56
+    assert ctypes.sizeof(N.Outputs) == 7 * 8
     assert ctypes.sizeof(N.Cathode) == 8 * (9 + 1 + 4 + 4) + 8 + 8 * 6 + 8 + 8
     assert ctypes.sizeof(N.Chamber) == 8 * 6 + 8
     assert ctypes.sizeof(N.Grid) == 8 * 11 + 16
@@ -76,6 +77,18 @@ def test_validation_rejects_bad_params():
         with pytest.raises(SpxError) as e:
             _create([si.single_ni(0.5, 10)], **kw)
         assert e.value.code == -1
+
+
+def test_arrival_edges_host_entry_point():
+    import numpy as np
+
+    import oracle
+    import paper_2411_14413_amd as spx
+    e64, c64, e32, c32 = spx.arrival_edges()
+    oe, oc = oracle.arrival_edges()
+    assert np.allclose(e64, oe, rtol=1e-15, atol=0) and np.allclose(c64, oc, rtol=0, atol=1e-15)
+    assert np.array_equal(e32, e64.astype(np.float32)) and np.array_equal(c32, c64.astype(np.float32))
+    assert np.all(np.diff(e64) > 0) and np.all(np.diff(c64) < 0)
 
 
 def test_area_centres_host_entry_point():

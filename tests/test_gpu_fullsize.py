@@ -38,7 +38,7 @@ def _run_full(cfgs, seed):
 
 def _check_integer_identities(plan, out):
     """Tallies = histogram of the records (on the GPU), counters = record sums, conservation."""
-    rec32 = out["records"].view(torch.int32).view(-1, 12)
+    rec32 = out["records"].view(torch.int32).view(-1, 14)
     st, bn, dif = rec32[:, 8], rec32[:, 9], rec32[:, 11]
     C = out["counters"].cpu().numpy()
     first = list(plan.first) + [plan.n_particles]
@@ -67,7 +67,7 @@ def _sampled_parity(plan, out, cfgs, seed, per_seg, rng):
     seg_ids, pids = np.array(seg_ids), np.array(pids)
     ref = oracle.run_list(cfgs, PARAMS, seed, seg_ids, pids)
     idx = torch.as_tensor(np.array(first)[seg_ids] + pids, device="cuda")
-    rec = spx.records_to_numpy(out["records"].view(-1, 48)[idx].reshape(-1))
+    rec = spx.records_to_numpy(out["records"].view(-1, 56)[idx].reshape(-1))
     m = match_stats(rec, ref, 1e-3)
     per = []
     for k in np.unique(seg_ids):
