@@ -32,7 +32,23 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
 RT_MAX = 256
-SEG_LEN = 52 + 2 * RT_MAX
+OBJ_LEN, OBJ_MAX = 16, 32
+SEG_LEN = 52 + 2 * RT_MAX + 1 + OBJ_LEN * OBJ_MAX
+OBJ_KIND = {"disc": 0, "rect": 1, "tube": 2}
+
+
+def segment_objects(cfg, k):
+    """Absorbing objects of cathode k's run: the configuration's absorbers, then (with
+    cross_absorb) the other targets as discs."""
+    objs = list(getattr(cfg, "absorbers", []) or [])
+    rows = []
+    for a in objs:
+        rows.append([OBJ_KIND[a.kind], *a.center, *a.normal, *a.u_axis, a.half_u, a.half_v, a.length])
+    if getattr(cfg, "cross_absorb", False):
+        for j, c in enumerate(cfg.cathodes):
+            if j != k:
+                rows.append([0, *c.center, *c.normal, *c.u_axis, c.radius, c.radius, 0.0])
+    return rows
 P_LEN = 8
 REC = 9
 STATE_DEPOSITED, STATE_WALL, STATE_ESCAPED = 1, 2, 3
@@ -213,6 +229,13 @@ def segments(cfgs: Sequence) -> np.ndarray:
             r[45] = len(prof)
             r[46:52] = cat.cos_coeff
             r[52:52 + 2 * len(prof)] = prof.ravel()
+            objs = segment_objects(cfg, k)
+            if len(objs) > OBJ_MAX:
+                raise ValueError(f"more than {OBJ_MAX} absorbing objects in one run")
+            base = 52 + 2 * RT_MAX
+            r[base] = len(objs)
+            for j, o in enumerate(objs):
+                r[base + 1 + OBJ_LEN * j: base + 1 + OBJ_LEN * j + len(o)] = o
             off += g.nu * g.nv
             rows.append(r)
     return np.ascontiguousarray(np.stack(rows))

@@ -323,10 +323,23 @@ enum {
     S_COS = 46,                /* c_0 .. c_5 of the emission law */
     S_RT = 52,                 /* (r_i, depth_i), i < RT_MAX */
     RT_MAX = 256,
-    S_LEN = S_RT + 2 * RT_MAX
+    S_OBJ_N = S_RT + 2 * RT_MAX,   /* absorbing objects of the segment */
+    S_OBJ = S_OBJ_N + 1,           /* OBJ_LEN doubles each: kind, c[3], n[3], u[3], half_u, half_v, length */
+    OBJ_LEN = 16, OBJ_MAX = 32,
+    S_LEN = S_OBJ + OBJ_LEN * OBJ_MAX
 };
+enum { OBJ_DISC = 0, OBJ_RECT = 1, OBJ_TUBE = 2 };
 /* Flat parameter layout. */
 enum { P_THETA_MIN = 0, P_ETH_KT, P_EVENT_CAP, P_NE, P_NS, P_LOGLO, P_LOGHI, P_LEN = 8 };
+
+/* An absorbing object ("dummy" object: mask, shutter, chimney, another target).  Planar
+ * disc (radius hu) or rectangle (half sizes hu, hv) with centre c, normal n, axes u, v; or an
+ * open tube: axis through c along n, radius hu, from c to c + len n.  Both faces absorb. */
+typedef struct {
+    int kind;
+    double c[3], n[3], u[3], v[3];
+    double hu, hv, len;
+} obj_t;
 
 typedef struct {
     uint32_t cfgcat;
@@ -345,6 +358,8 @@ typedef struct {
     double n_mm3, kT, vth, vg;           /* vth = sqrt(kT/Mg) per Cartesian component; vg = sqrt(2kT/Mg) */
     double E_th, lam_th;
     int gas_motion;
+    int n_obj;
+    obj_t obj[OBJ_MAX];
     uint64_t N, bin_off;
 } seg_t;
 
@@ -487,6 +502,15 @@ static void seg_init(const double* r, const double* prm, const tab_t* tb, seg_t*
     } else {
         s->lam_th = INFINITY;
     }
+    s->n_obj = (int)r[S_OBJ_N];
+    for (int k = 0; k < s->n_obj; ++k) {
+        const double* o = r + S_OBJ + OBJ_LEN * k;
+        obj_t* b = &s->obj[k];
+        b->kind = (int)o[0];
+        for (int i = 0; i < 3; ++i) { b->c[i] = o[1 + i]; b->n[i] = o[4 + i]; b->u[i] = o[7 + i]; }
+        cross(b->n, b->u, b->v);
+        b->hu = o[10]; b->hv = o[11]; b->len = o[12];
+    }
     s->N = (uint64_t)r[S_N];
     s->bin_off = (uint64_t)r[S_BINOFF];
 }
@@ -593,7 +617,7 @@ static void launch(const seg_t* s, uint64_t seed, uint32_t pid, double x[3], dou
 
 /* ------------------------------------------------------------------------- */
 /* Surface intersection.  Returns nearest hit with 0 < t <= ell; ties keep the */
-/* first in the order substrate, cathode, chamber.                            */
+/* first in the order substrate, cathode, objects, chamber.                   */
 /* ------------------------------------------------------------------------- */
 typedef struct { double t; int state; int bin; } hit_t;
 
@@ -649,6 +673,45 @@ static hit_t hit_test(const seg_t* s, const double x[3], const double d[3], doub
                 }
             }
         }
+    }
+    /* absorbing objects: discs and rectangles (a plane crossing inside the region), open
+     * tubes (the smaller positive root of the distance to the axis with its axial
+     * coordinate inside the tube) */
+    for (int k = 0; k < s->n_obj; ++k) {
+        const obj_t* b = &s->obj[k];
+        double t = INFINITY;
+        if (b->kind == OBJ_DISC || b->kind == OBJ_RECT) {
+            const double dn = dot(d, b->n);
+            if (dn != 0.0) {
+                double w[3] = {b->c[0] - x[0], b->c[1] - x[1], b->c[2] - x[2]};
+                const double tp = dot(w, b->n) / dn;
+                if (tp > 0.0) {
+                    double q[3];
+                    for (int i = 0; i < 3; ++i) q[i] = x[i] + tp * d[i] - b->c[i];
+                    const double qu = dot(q, b->u), qv = dot(q, b->v);
+                    const int in = (b->kind == OBJ_DISC) ? (qu * qu + qv * qv <= b->hu * b->hu)
+                                                         : (fabs(qu) <= b->hu && fabs(qv) <= b->hv);
+                    if (in) t = tp;
+                }
+            }
+        } else {
+            double w[3] = {x[0] - b->c[0], x[1] - b->c[1], x[2] - b->c[2]};
+            const double wa = dot(w, b->n), da = dot(d, b->n);
+            double wp[3], dp[3];
+            for (int i = 0; i < 3; ++i) { wp[i] = w[i] - wa * b->n[i]; dp[i] = d[i] - da * b->n[i]; }
+            const double A = dot(dp, dp), B = dot(wp, dp), C = dot(wp, wp) - b->hu * b->hu;
+            const double D = B * B - A * C;
+            if (A > 0.0 && D >= 0.0) {
+                const double sq = sqrt(D);
+                const double roots[2] = {(-B - sq) / A, (-B + sq) / A};
+                for (int j = 0; j < 2; ++j) {
+                    const double tr = roots[j];
+                    const double za = wa + tr * da;
+                    if (tr > 0.0 && za >= 0.0 && za <= b->len) { t = tr; break; }
+                }
+            }
+        }
+        if (t < best.t) { best.t = t; best.state = OR_WALL; best.bin = -1; }
     }
     /* chamber: cylinder side and the two caps (closed: some t >= 0 always exists) */
     {

@@ -95,10 +95,26 @@ class Cathode:
 
 
 @dataclass
+class Absorber:
+    """An absorbing "dummy" object (mask, shutter, chimney).  kind "disc" (radius half_u),
+    "rect" (half sizes half_u x half_v along u_axis and normal x u_axis) or "tube" (an open
+    cylinder: axis from center along normal, radius half_u, length).  Both faces absorb."""
+    kind: str = "disc"
+    center: Vec3 = (0.0, 0.0, 150.0)
+    normal: Vec3 = (0.0, 0.0, 1.0)
+    u_axis: Vec3 = (1.0, 0.0, 0.0)
+    half_u: float = 10.0
+    half_v: float = 10.0
+    length: float = 0.0
+
+
+@dataclass
 class Config:
     chamber: Chamber
     grid: Grid
     cathodes: List[Cathode]
+    absorbers: List[Absorber] = field(default_factory=list)
+    cross_absorb: bool = False     # the other targets of the configuration absorb too
 
 
 @dataclass
@@ -169,7 +185,7 @@ def with_launch(cfg: Config, rt_profile=None, cos_coeff=None) -> Config:
     cats = [replace(c, rt_profile=rt_profile if rt_profile is not None else c.rt_profile,
                     cos_coeff=tuple(cos_coeff) if cos_coeff is not None else c.cos_coeff)
             for c in cfg.cathodes]
-    return Config(chamber=cfg.chamber, grid=cfg.grid, cathodes=cats)
+    return replace(cfg, cathodes=cats)
 
 
 # ---------------------------------------------------------------------------
