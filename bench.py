@@ -96,6 +96,10 @@ def workload(name, scale=1.0):
     if name == "quaternary":
         cfg = si.quaternary()
         return [cfg], "four confocal cathodes Ni/Pd/Pt/Ru, tilt 25 deg, 150 mm, Ar 0.5 Pa, 100 mm wafer 200x200 bins, 2.3e7 particles"
+    if name == "quaternary_chimneys":
+        cfg = si.with_chimneys(si.quaternary())
+        return [cfg], ("four confocal cathodes Ni/Pd/Pt/Ru, tilt 25 deg, 150 mm, Ar 0.5 Pa, 100 mm wafer 200x200 bins, "
+                       "2.3e7 particles; each target in a 30 mm open chimney (radius + 5 mm), the other targets absorb")
     if name == "sweep":
         cfgs = si.quaternary_sweep(64, scale=scale)
         return cfgs, "64 four-cathode chambers: p U(0.1,2) Pa, tilt U(0,40) deg, distance U(80,200) mm, 1e5-1e7 particles each"
@@ -158,7 +162,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="legs", choices=["legs", "legs_measured", "quaternary", "sweep"])
+    ap.add_argument("--workload", default="legs", choices=["legs", "legs_measured", "quaternary", "quaternary_chimneys", "sweep"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")

@@ -108,12 +108,34 @@ typedef struct spx_grid {
     int32_t reserved0;
 } spx_grid;
 
+/* An absorbing "dummy" object (Methods, "The SIMTRA model": masks, shutters, chimneys
+ * collect the atoms that reach them); both faces absorb (the atom ends as SPX_WALL). */
+#define SPX_OBJ_DISC 0   /* disc: centre, unit normal, radius = half_u */
+#define SPX_OBJ_RECT 1   /* rectangle: centre, unit normal, unit u_axis, half sizes half_u x half_v */
+#define SPX_OBJ_TUBE 2   /* open cylinder (chimney): axis from centre along the unit normal,
+                            radius = half_u, length; no end caps */
+typedef struct spx_object {
+    int32_t kind;
+    int32_t reserved0;
+    double center[3];
+    double normal[3];
+    double u_axis[3];            /* rectangles only (v = normal x u_axis) */
+    double half_u, half_v;       /* mm */
+    double length;               /* tubes, mm */
+} spx_object;
+
 typedef struct spx_config {
     spx_chamber chamber;
     spx_grid grid;
     int32_t n_cathodes;          /* 1 .. 255 */
-    int32_t reserved0;
+    int32_t cross_absorb;        /* 1: the other targets of this configuration absorb (lifts the
+                                    no-cross-deposition assumption of split single-cathode runs,
+                                    "The SIMTRA Python wrapper"); 0: each run holds its own target only */
     const spx_cathode* cathodes; /* host array of n_cathodes; deep-copied by spx_plan_create */
+    int32_t n_objects;           /* absorbing objects of this configuration; with cross_absorb,
+                                    n_objects + n_cathodes - 1 <= 32 */
+    int32_t reserved1;
+    const spx_object* objects;   /* host array of n_objects (deep-copied; NULL if none) */
 } spx_config;
 
 typedef struct spx_params {
@@ -169,8 +191,9 @@ typedef struct spx_plan spx_plan;
  * a cathode or substrate outside the chamber, nu*nv > 2^24 or < 1, rt_lo >= rt_hi (rt_n == 0),
  * an invalid racetrack profile (rt_n == 1 or > 256, radii not increasing, outside [0, radius],
  * negative depths, zero weight), E_max <= 0, masses <= 0, an emission law negative somewhere on
- * [0, 90 deg] or with zero integral, non-unit or non-orthogonal axes, more than 2^24
- * configurations.  *out is set only on success. */
+ * [0, 90 deg] or with zero integral, non-unit or non-orthogonal axes, an object of unknown kind,
+ * with non-positive sizes or outside the chamber, more than 32 absorbing objects in one run,
+ * more than 2^24 configurations.  *out is set only on success. */
 int spx_plan_create(const spx_config* h_cfgs, int32_t n_cfgs, const spx_params* h_params, spx_plan** out);
 
 /* Sizes of spx_run's outputs: total tally bins over all segments, counters

@@ -105,6 +105,21 @@ class Plan:
             self._keep.append(cats)
             C.n_cathodes = len(cfg.cathodes)
             C.cathodes = ctypes.cast(cats, ctypes.POINTER(N.Cathode))
+            C.cross_absorb = 1 if getattr(cfg, "cross_absorb", False) else 0
+            absorbers = list(getattr(cfg, "absorbers", []) or [])
+            kinds = {"disc": 0, "rect": 1, "tube": 2}
+            if absorbers:
+                objs = (N.Object * len(absorbers))()
+                for j, a in enumerate(absorbers):
+                    O = objs[j]
+                    O.kind = kinds[a.kind]
+                    O.center, O.normal, O.u_axis = _vec(a.center), _vec(a.normal), _vec(a.u_axis)
+                    O.half_u, O.half_v, O.length = a.half_u, a.half_v, a.length
+                self._keep.append(objs)
+                C.n_objects = len(absorbers)
+                C.objects = ctypes.cast(objs, ctypes.POINTER(N.Object))
+            else:
+                C.n_objects = 0
         self._p = _params(params, precision)
         h = ctypes.c_void_p()
         check(L.spx_plan_create(carr, n, ctypes.byref(self._p), ctypes.byref(h)), "spx_plan_create")

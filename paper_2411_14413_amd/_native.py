@@ -41,9 +41,16 @@ class Grid(ctypes.Structure):
                 ("nv", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
 
+class Object(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("center", ctypes.c_double * 3),
+                ("normal", ctypes.c_double * 3), ("u_axis", ctypes.c_double * 3), ("half_u", ctypes.c_double),
+                ("half_v", ctypes.c_double), ("length", ctypes.c_double)]
+
+
 class Config(ctypes.Structure):
     _fields_ = [("chamber", Chamber), ("grid", Grid), ("n_cathodes", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("cathodes", ctypes.POINTER(Cathode))]
+                ("cross_absorb", ctypes.c_int32), ("cathodes", ctypes.POINTER(Cathode)),
+                ("n_objects", ctypes.c_int32), ("reserved1", ctypes.c_int32), ("objects", ctypes.POINTER(Object))]
 
 
 class Params(ctypes.Structure):

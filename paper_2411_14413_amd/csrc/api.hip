@@ -32,6 +32,17 @@ void cross(const double* a, const double* b, double* c)
 }
 double dot(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 bool unit(const double* a) { return std::fabs(std::sqrt(dot(a, a)) - 1.0) < 1e-9; }
+// A unit vector perpendicular to the unit vector n.
+void perp_axis(const double* n, double* u)
+{
+    const double a[3] = {std::fabs(n[0]) < 0.9 ? 1.0 : 0.0, std::fabs(n[0]) < 0.9 ? 0.0 : 1.0, 0.0};
+    double c[3];
+    c[0] = n[1] * a[2] - n[2] * a[1];
+    c[1] = n[2] * a[0] - n[0] * a[2];
+    c[2] = n[0] * a[1] - n[1] * a[0];
+    const double l = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    for (int i = 0; i < 3; ++i) u[i] = c[i] / l;
+}
 bool inside_chamber(const spx_chamber& ch, const double* p)
 {
     return std::hypot(p[0], p[1]) <= ch.radius * (1.0 + 1e-12) && p[2] >= ch.z_lo && p[2] <= ch.z_hi;
@@ -150,6 +161,43 @@ static int validate(const spx_config* cfgs, int n_cfgs, const spx_params* p)
             if (K.n_particles >= (1ull << 32)) return fail(wk + "n_particles must be < 2^32");
             total += K.n_particles;
         }
+        if (C.n_objects < 0 || (C.n_objects > 0 && !C.objects)) return fail(w + "bad object list");
+        if (C.n_objects + (C.cross_absorb ? C.n_cathodes - 1 : 0) > OBJ_MAX_SEG)
+            return fail(w + "more than " + std::to_string(OBJ_MAX_SEG) + " absorbing objects in one run");
+        for (int j = 0; j < C.n_objects; ++j) {
+            const spx_object& O = C.objects[j];
+            const std::string wo = w + "object " + std::to_string(j) + ": ";
+            if (O.kind < SPX_OBJ_DISC || O.kind > SPX_OBJ_TUBE) return fail(wo + "unknown kind");
+            if (!unit(O.normal)) return fail(wo + "normal must be a unit vector");
+            if (!(O.half_u > 0.0)) return fail(wo + "half_u must be > 0");
+            double ou[3], ov[3];
+            if (O.kind == SPX_OBJ_RECT) {
+                if (!unit(O.u_axis) || std::fabs(dot(O.normal, O.u_axis)) > 1e-9)
+                    return fail(wo + "normal and u_axis must be orthonormal");
+                if (!(O.half_v > 0.0)) return fail(wo + "half_v must be > 0");
+                for (int i = 0; i < 3; ++i) ou[i] = O.u_axis[i];
+            } else {
+                perp_axis(O.normal, ou);
+            }
+            cross(O.normal, ou, ov);
+            bool inside = true;
+            if (O.kind == SPX_OBJ_DISC) {
+                inside = disc_inside(ch, O.center, ou, ov, O.half_u);
+            } else if (O.kind == SPX_OBJ_RECT) {
+                for (int a = -1; a <= 1; a += 2)
+                    for (int b = -1; b <= 1; b += 2) {
+                        double q[3];
+                        for (int i = 0; i < 3; ++i) q[i] = O.center[i] + a * O.half_u * ou[i] + b * O.half_v * ov[i];
+                        inside = inside && inside_chamber(ch, q);
+                    }
+            } else {
+                if (!(O.length > 0.0)) return fail(wo + "tube length must be > 0");
+                double top[3];
+                for (int i = 0; i < 3; ++i) top[i] = O.center[i] + O.length * O.normal[i];
+                inside = disc_inside(ch, O.center, ou, ov, O.half_u) && disc_inside(ch, top, ou, ov, O.half_u);
+            }
+            if (!inside) return fail(wo + "object outside the chamber");
+        }
     }
     if (total == 0) return fail("every cathode has n_particles == 0");
     return SPX_OK;
@@ -198,6 +246,24 @@ static void derive(Plan* P, const spx_config* cfgs, int n_cfgs)
                 s.rt_d.push_back(K.rt_profile[2 * i + 1]);
             }
             for (int i = 0; i < 6; ++i) s.cosc[i] = K.cos_coeff[i];
+            // absorbing objects of this run: the configuration's, then the other targets
+            for (int j = 0; j < C.n_objects; ++j) s.objs.push_back(C.objects[j]);
+            if (C.cross_absorb)
+                for (int j = 0; j < C.n_cathodes; ++j) {
+                    if (j == k) continue;
+                    spx_object o{};
+                    o.kind = SPX_OBJ_DISC;
+                    for (int i = 0; i < 3; ++i) {
+                        o.center[i] = C.cathodes[j].center[i];
+                        o.normal[i] = C.cathodes[j].normal[i];
+                    }
+                    o.half_u = o.half_v = C.cathodes[j].radius;
+                    s.objs.push_back(o);
+                }
+            for (auto& o : s.objs) {
+                o.center[2] -= s.z_mid;
+                if (o.kind != SPX_OBJ_RECT) perp_axis(o.normal, o.u_axis);
+            }
             const double al = (K.rt_lo - K.rt_mu) / K.rt_sigma, be = (K.rt_hi - K.rt_mu) / K.rt_sigma;
             s.PhiA = norm_cdf(al);
             s.QB = norm_cdf(-be);
@@ -296,6 +362,8 @@ template <typename R> static SegDev<R> to_device(const Plan* P, const SegHost& s
     d.gas_motion = s.gas_motion;
     d.vacuum = s.n_mm3 > 0.0 ? 0 : 1;
     d.rt = nullptr;                          // set once the racetrack tables are on the device
+    d.obj = nullptr;                         // set once the objects are on the device
+    d.n_obj = (int32_t)s.objs.size();
     d.rt_n = (int32_t)s.rt_r.size();
     double norm = 0.0;
     bool pure = true;
@@ -330,7 +398,7 @@ static void release(Plan* P)
     if (P->graph) (void)hipGraphDestroy(P->graph);
     void* ptrs[] = {P->d_theta64, P->d_betamax64, P->d_theta32, P->d_betamax32, P->d_seg32,   P->d_seg64,
                     P->d_tfirst,  P->d_torder,    P->d_qstate,  P->d_queue,     P->d_bin_off, P->d_seg_norm,
-                    P->d_rt32,    P->d_rt64,      P->d_edges32, P->d_edges64};
+                    P->d_rt32,    P->d_rt64,      P->d_edges32, P->d_edges64, P->d_obj32,   P->d_obj64};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (hipEvent_t e : P->phase_events) (void)hipEventDestroy(e);
@@ -434,6 +502,67 @@ static int create(const spx_config* cfgs, int n_cfgs, const spx_params* prm, Pla
             const bool last = i + 1 == m;
             rt64.push_back(RtNode<double>{sg.rt_r[i], last ? 1.0 : F[i] / Z, p1[i] / Z, p2[i] / Z, p3[i] / Z,
                                           last ? 0.0 : sg.rt_r[i + 1] - sg.rt_r[i]});
+        }
+    }
+    {
+        // absorbing objects: per segment a run of ObjDev in one array (FP32 and FP64)
+        std::vector<ObjDev<double>> ob64;
+        std::vector<size_t> ob_off(n, 0);
+        for (int k = 0; k < n; ++k) {
+            ob_off[k] = ob64.size();
+            for (const auto& o : P->seg[k].objs) {
+                ObjDev<double> q{};
+                q.kind = o.kind;
+                double v[3];
+                cross(o.normal, o.u_axis, v);
+                for (int i = 0; i < 3; ++i) {
+                    q.c[i] = o.center[i];
+                    q.n[i] = o.normal[i];
+                    q.u[i] = o.u_axis[i];
+                    q.v[i] = v[i];
+                }
+                q.nc = dot(o.normal, o.center);
+                q.uc = dot(o.u_axis, o.center);
+                q.vc = dot(v, o.center);
+                q.hu = o.half_u;
+                q.hv = o.kind == SPX_OBJ_RECT ? o.half_v : o.half_u;
+                q.r2 = o.half_u * o.half_u;
+                q.len = o.length;
+                ob64.push_back(q);
+            }
+        }
+        if (!ob64.empty()) {
+            std::vector<ObjDev<float>> ob32;
+            for (const auto& q : ob64) {
+                ObjDev<float> f{};
+                f.kind = q.kind;
+                for (int i = 0; i < 3; ++i) {
+                    f.c[i] = (float)q.c[i];
+                    f.n[i] = (float)q.n[i];
+                    f.u[i] = (float)q.u[i];
+                    f.v[i] = (float)q.v[i];
+                }
+                f.nc = (float)q.nc;
+                f.uc = (float)q.uc;
+                f.vc = (float)q.vc;
+                f.hu = (float)q.hu;
+                f.hv = (float)q.hv;
+                f.r2 = (float)q.r2;
+                f.len = (float)q.len;
+                ob32.push_back(f);
+            }
+            if (dalloc(&P->d_obj32, ob32.size()) != SPX_OK || dalloc(&P->d_obj64, ob64.size()) != SPX_OK ||
+                hipMemcpy(P->d_obj32, ob32.data(), sizeof(ObjDev<float>) * ob32.size(), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(P->d_obj64, ob64.data(), sizeof(ObjDev<double>) * ob64.size(), hipMemcpyHostToDevice) != hipSuccess) {
+                set_error("copying the absorbing objects to the device failed");
+                release(P);
+                return SPX_EDEVICE;
+            }
+            for (int k = 0; k < n; ++k)
+                if (!P->seg[k].objs.empty()) {
+                    s32[k].obj = P->d_obj32 + ob_off[k];
+                    s64[k].obj = P->d_obj64 + ob_off[k];
+                }
         }
     }
     {

@@ -143,6 +143,16 @@ template <typename R> struct RtNode {
     R r, C, p1, p2, p3, dr;
 };
 
+// An absorbing object of a segment (chamber frame).  Planar (disc, rectangle): centre c,
+// normal n, axes u, v with nc = n.c, uc = u.c, vc = v.c, half sizes hu, hv (discs: r2 = hu^2).
+// Tube: axis through c along n, r2 = radius^2, length len.
+template <typename R> struct ObjDev {
+    int32_t kind, pad;
+    R c[3], n[3], u[3], v[3];
+    R nc, uc, vc;
+    R hu, hv, r2, len;
+};
+
 template <typename R> struct SegDev {
     R cat_c[3], cat_n[3], cat_u[3], cat_v[3];
     R cat_R2;
@@ -153,6 +163,7 @@ template <typename R> struct SegDev {
     R ch_R2, zlo, zhi;
     R rt_mu, rt_sig, PhiA, QB, dPhi;      // racetrack truncated normal
     const RtNode<R>* rt;                  // measured racetrack (rt_n nodes), else nullptr
+    const ObjDev<R>* obj;                 // absorbing objects (n_obj), else nullptr
     R cosk[6];                            // emission law: G(mu) = sum cosk_i mu^(i+1) rises from 0 to 1
     R Us, smax;                           // Thompson inverse CDF
     R two_over_Ms, half_Ms;               // v = sqrt(2E/Ms), E = Ms v^2 / 2
@@ -166,7 +177,7 @@ template <typename R> struct SegDev {
     R z_mid;                              // chamber-frame origin along z (world z = z' + z_mid)
     int32_t shape, nu, nv, gas_motion;
     int32_t vacuum, rt_n;
-    int32_t cos_pure, pad0;               // cos_pure: the cosine law, cos(theta) = sqrt(RN)
+    int32_t cos_pure, n_obj;              // cos_pure: the cosine law, cos(theta) = sqrt(RN)
     uint32_t cfgcat;                      // (config << 8) | cathode: third Philox counter word
     uint32_t pad1;
     uint64_t bin_off;                     // first bin of this segment in the tally
@@ -322,12 +333,14 @@ struct HitF {
     int state;     // HIT_NONE / HIT_DEPOSITED / HIT_WALL
 };
 
-// Nearest surface with 0 < t <= ell; exact ties keep substrate, then cathode, then chamber.
-// Planes use the precomputed n.c, u.c, v.c: t = (n.c - n.x)/(n.d), q.u = u.x + t u.d - u.c.
-// Written without branches (every candidate computed, then selected) so that the whole
-// test is one basic block: a wave runs it once whatever its lanes need, and the loads of
-// the surface constants can be scheduled early.  A direction parallel to a plane gives a
-// reciprocal of zero, hence t = inf or NaN, which fails t > 0 as intended.
+// Nearest surface with 0 < t <= ell; exact ties keep substrate, then cathode, then the
+// absorbing objects in order, then chamber.  Planes use the precomputed n.c, u.c, v.c:
+// t = (n.c - n.x)/(n.d), q.u = u.x + t u.d - u.c.  The fixed surfaces are written without
+// branches (every candidate computed, then selected) so that they form one basic block: a
+// wave runs them once whatever its lanes need, and the loads of the surface constants can be
+// scheduled early; the objects follow in a loop uniform over the segment.  A direction
+// parallel to a plane gives a reciprocal of zero, hence t = inf or NaN, which fails t > 0 as
+// intended.
 template <typename R>
 __device__ __forceinline__ HitF hit_test(const SegDev<R>& s, const R* x, const R* d, R ell, R& t_hit, R& qu_hit,
                                          R& qv_hit, bool first)
@@ -353,6 +366,38 @@ __device__ __forceinline__ HitF hit_test(const SegDev<R>& s, const R* x, const R
     const bool hit_c = !first && (tcat > (R)0) && (tcat < best) && (cu * cu + cv * cv <= s.cat_R2);
     best = hit_c ? tcat : best;
     state = hit_c ? HIT_WALL : state;
+    // absorbing objects (both faces): a plane crossing inside the disc or rectangle; for a tube
+    // the smaller positive root of |w_perp + t d_perp| = radius whose axial coordinate lies
+    // in [0, len]
+    for (int k = 0; k < s.n_obj; ++k) {
+        const ObjDev<R>& o = s.obj[k];
+        R to = inf;
+        if (o.kind != 2) {
+            const R dn_o = dot3(d, o.n);
+            const R tp = (o.nc - dot3(x, o.n)) * m_rcp(dn_o);
+            const R ou = dot3(x, o.u) + tp * dot3(d, o.u) - o.uc;
+            const R ov = dot3(x, o.v) + tp * dot3(d, o.v) - o.vc;
+            const bool in = (o.kind == 0) ? (ou * ou + ov * ov <= o.r2) : (fabs(ou) <= o.hu && fabs(ov) <= o.hv);
+            to = (tp > (R)0 && in) ? tp : inf;
+        } else {
+            const R w[3] = {x[0] - o.c[0], x[1] - o.c[1], x[2] - o.c[2]};
+            const R wa = dot3(w, o.n), da = dot3(d, o.n);
+            const R wp[3] = {w[0] - wa * o.n[0], w[1] - wa * o.n[1], w[2] - wa * o.n[2]};
+            const R dp[3] = {d[0] - da * o.n[0], d[1] - da * o.n[1], d[2] - da * o.n[2]};
+            const R A = dot3(dp, dp), B = dot3(wp, dp), C = dot3(wp, wp) - o.r2;
+            const R D = B * B - A * C;
+            if (A > (R)0 && D >= (R)0) {
+                const R sq = m_sqrt(D), ia = m_rcp(A);
+                const R t1 = (-B - sq) * ia, t2 = (-B + sq) * ia;
+                const R z1 = wa + t1 * da, z2 = wa + t2 * da;
+                if (t1 > (R)0 && z1 >= (R)0 && z1 <= o.len) to = t1;
+                else if (t2 > (R)0 && z2 >= (R)0 && z2 <= o.len) to = t2;
+            }
+        }
+        const bool hit_o = to < best;
+        best = hit_o ? to : best;
+        state = hit_o ? HIT_WALL : state;
+    }
     // chamber: cylinder side (stable root of |x + t d|^2 = R^2 in the xy-plane) and caps
     const R a = d[0] * d[0] + d[1] * d[1];
     const R b = x[0] * d[0] + x[1] * d[1];
@@ -374,8 +419,9 @@ __device__ __forceinline__ HitF hit_test(const SegDev<R>& s, const R* x, const R
 }
 
 // Distance from x to the nearest absorbing surface the surface test knows (never more than
-// the true distance): the substrate plate and the target disc as point-to-region
-// distances, the chamber side and caps.  A path that stays closer to x than this cannot
+// the true distance): the substrate plate, the target disc and the planar objects as
+// point-to-region distances, tubes as point-to-open-cylinder distances, the chamber side and
+// caps.  A path that stays closer to x than this cannot
 // meet any surface.
 template <typename R> __device__ __forceinline__ R clearance(const SegDev<R>& s, const R* x)
 {
@@ -394,9 +440,36 @@ template <typename R> __device__ __forceinline__ R clearance(const SegDev<R>& s,
     const R cu = dot3(x, s.cat_u) - s.cat_uc, cv = dot3(x, s.cat_v) - s.cat_vc;
     const R ec = fmax(m_sqrt(cu * cu + cv * cv) - m_sqrt(s.cat_R2), (R)0);
     const R d_cat2 = hc * hc + ec * ec;
+    R dmin2 = fmin(d_sub2, d_cat2);
+    for (int k = 0; k < s.n_obj; ++k) {
+        const ObjDev<R>& o = s.obj[k];
+        R d2;
+        if (o.kind != 2) {
+            const R ho = dot3(x, o.n) - o.nc;
+            const R ou = dot3(x, o.u) - o.uc, ov = dot3(x, o.v) - o.vc;
+            R e2;
+            if (o.kind == 0) {
+                const R er = fmax(m_sqrt(ou * ou + ov * ov) - o.hu, (R)0);
+                e2 = er * er;
+            } else {
+                const R eu = fmax(fabs(ou) - o.hu, (R)0), ev = fmax(fabs(ov) - o.hv, (R)0);
+                e2 = eu * eu + ev * ev;
+            }
+            d2 = ho * ho + e2;
+        } else {
+            // open cylinder: radial distance to the wall, plus the axial overhang past a rim
+            const R w[3] = {x[0] - o.c[0], x[1] - o.c[1], x[2] - o.c[2]};
+            const R wa = dot3(w, o.n);
+            const R rp = m_sqrt(fmax(dot3(w, w) - wa * wa, (R)0));
+            const R dr = rp - o.hu;
+            const R off = fmax(fmax(-wa, wa - o.len), (R)0);
+            d2 = dr * dr + off * off;
+        }
+        dmin2 = fmin(dmin2, d2);
+    }
     const R side = m_sqrt(s.ch_R2) - m_sqrt(x[0] * x[0] + x[1] * x[1]);
     const R caps = fmin(x[2] - s.zlo, s.zhi - x[2]);
-    return fmin(m_sqrt(fmin(d_sub2, d_cat2)), fmin(side, caps));
+    return fmin(m_sqrt(dmin2), fmin(side, caps));
 }
 
 // Tally bin of a deposit at in-plane coordinates (qu, qv) of the substrate (clamped).

@@ -44,6 +44,7 @@ struct SegHost {
     int gas_motion;
     double pressure;
     std::vector<double> rt_r, rt_d;   // measured racetrack nodes (empty: truncated normal)
+    std::vector<spx_object> objs;     // absorbing objects of the run (chamber frame)
     double cosc[6];                   // emission law coefficients
     uint64_t N, bin_off, first_rec;
     double cost;          // relative expected work per particle (ticket ordering)
@@ -107,6 +108,7 @@ constexpr uint64_t QUEUE_CHUNK = 64;         // queue slots a wave reserves per 
 constexpr uint64_t QUEUE_SLACK_WAVES = 8192;  // waves that may leave slots unused (32 per CU, 256 CUs)
 constexpr size_t LDS_COUNTERS_MAX = 16384;   // bytes: up to 292 segments
 constexpr int RT_MAX_NODES = 256;             // nodes of a measured racetrack profile
+constexpr int OBJ_MAX_SEG = 32;               // absorbing objects of one (config, cathode) run
 constexpr uint64_t TICKET_CHUNK = 64;        // tickets a wave claims per global atomic
 constexpr int DEFER_MIN = 8;                  // held diffusive steps that trigger a wave's surface tests
 constexpr int COOP_MAX = 8;                   // drained waves with at most this many live lanes walk cooperatively
@@ -152,6 +154,8 @@ struct spx_plan {
     spx::SegDev<double>* d_seg64 = nullptr;
     float* d_edges32 = nullptr;               // arrival bin edges: energy [61] then cos [91]
     double* d_edges64 = nullptr;
+    spx::ObjDev<float>* d_obj32 = nullptr;    // absorbing objects of all segments
+    spx::ObjDev<double>* d_obj64 = nullptr;
     spx::RtNode<float>* d_rt32 = nullptr;     // measured racetracks of all segments
     spx::RtNode<double>* d_rt64 = nullptr;
     uint64_t* d_tfirst = nullptr;

@@ -188,6 +188,15 @@ def with_launch(cfg: Config, rt_profile=None, cos_coeff=None) -> Config:
     return replace(cfg, cathodes=cats)
 
 
+def with_chimneys(cfg: Config, length: float = 30.0, gap: float = 5.0, cross_absorb: bool = True) -> Config:
+    """Copy of cfg with an open chimney around each target (coaxial tube of radius
+    target radius + gap from the target plane along its normal, ``length`` mm long), keeping
+    the configuration's other absorbers; with cross_absorb the other targets absorb too."""
+    tubes = [Absorber("tube", center=c.center, normal=c.normal, u_axis=c.u_axis, half_u=c.radius + gap,
+                      half_v=c.radius + gap, length=length) for c in cfg.cathodes]
+    return replace(cfg, absorbers=list(cfg.absorbers) + tubes, cross_absorb=cross_absorb)
+
+
 # ---------------------------------------------------------------------------
 # Four confocal cathodes (Ni, Pd, Pt, Ru) around a 100 mm wafer.
 # ---------------------------------------------------------------------------

@@ -37,3 +37,23 @@ def records_histogram(rec, n_bins_seg, first, counts_len):
         dep = r[r["state"] == 1]
         out.append(np.bincount(dep["bin"].astype(np.int64), minlength=nb))
     return out
+
+
+def bin_flips_off_edge(rec, ref, tol, grid):
+    """Matched deposits (same state, end points within tol) whose bins differ although the
+    oracle's end point lies farther than tol from every bin edge of the substrate grid: such a
+    flip cannot come from rounding of the end point.  Returns their count."""
+    st_g = rec["state"].astype(np.int64)
+    d = np.linalg.norm(gpu_positions(rec) - ref[:, :3], axis=1)
+    dep = (st_g == 1) & (ref[:, 3].astype(np.int64) == 1) & (d < tol)
+    flip = dep & (rec["bin"].astype(np.int64) != ref[:, 4].astype(np.int64))
+    if not flip.any():
+        return 0
+    c, n, u = (np.asarray(v, dtype=np.float64) for v in (grid.center, grid.normal, grid.u_axis))
+    v = np.cross(n, u)
+    q = ref[flip, :3] - c
+    du, dv = 2 * grid.half_u / grid.nu, 2 * grid.half_v / grid.nv
+    fu = (q @ u + grid.half_u) / du
+    fv = (q @ v + grid.half_v) / dv
+    edge = np.minimum(np.abs(fu - np.rint(fu)) * du, np.abs(fv - np.rint(fv)) * dv)
+    return int((edge > tol).sum())

@@ -35,6 +35,8 @@ def test_header_struct_sizes_match_binding():
     assert ctypes.sizeof(N.Cathode) == 8 * (9 + 1 + 4 + 4) + 8 + 8 * 6 + 8 + 8
     assert ctypes.sizeof(N.Chamber) == 8 * 6 + 8
     assert ctypes.sizeof(N.Grid) == 8 * 11 + 16
+    assert ctypes.sizeof(N.Object) == 8 + 8 * 12
+    assert ctypes.sizeof(N.Config) == ctypes.sizeof(N.Chamber) + ctypes.sizeof(N.Grid) + 8 + 8 + 8 + 8
 
 
 def _create(cfgs, **kw):
@@ -60,6 +62,19 @@ def _create(cfgs, **kw):
     (lambda c: setattr(c.grid, "nu", 0), "nu"),
     (lambda c: setattr(c.grid, "normal", (0.0, 0.0, -2.0)), "orthonormal"),
     (lambda c: setattr(c, "cathodes", []), "cathodes"),
+    (lambda c: setattr(c, "absorbers", [si.Absorber("tube", (0, 0, 0), (0, 0, 1), half_u=10.0, length=0.0)]),
+     "length"),
+    (lambda c: setattr(c, "absorbers", [si.Absorber("disc", (0, 0, 0), (0, 0, 2), half_u=10.0)]), "unit vector"),
+    (lambda c: setattr(c, "absorbers", [si.Absorber("disc", (0, 0, 0), (0, 0, 1), half_u=0.0)]), "half_u"),
+    (lambda c: setattr(c, "absorbers", [si.Absorber("rect", (0, 0, 50), (0, 0, 1), (0, 1, 1), 5.0, 5.0)]),
+     "orthonormal"),
+    (lambda c: setattr(c, "absorbers", [si.Absorber("rect", (0, 0, 50), (0, 0, 1), (1, 0, 0), 5.0, 0.0)]),
+     "half_v"),
+    (lambda c: setattr(c, "absorbers", [si.Absorber("disc", (0, 0, 50), (0, 0, 1), half_u=500.0)]), "outside"),
+    (lambda c: setattr(c, "absorbers", [si.Absorber("tube", (0, 0, 50), (0, 0, 1), half_u=5.0, length=900.0)]),
+     "outside"),
+    (lambda c: setattr(c, "absorbers", [si.Absorber("disc", (0, 0, 50), (0, 0, 1), half_u=1.0)] * 33),
+     "absorbing objects"),
 ])
 def test_validation_rejects_bad_configs(mutate, msg):
     from paper_2411_14413_amd import SpxError
