@@ -16,7 +16,10 @@ holds the post-processing steps in numpy/torch-CPU float64:
   density over atomic mass, to at.% (Methods, the calculation paragraph, and the
   Introduction on the linear power-rate relation);
 * the squared Euclidean distance d_e^2 of compositions (Results, d_e equation);
-* the least-squares power-rate line (Supporting Information, Table S1).
+* the least-squares power-rate line (Supporting Information, Table S1);
+* the tilt inversion (Results, the cathode-tilt study and its Figure 8): compositions of a
+  library per sweep point, the compositional area a ternary library covers, and the sweep
+  point that best explains a measured library.
 """
 from __future__ import annotations
 
@@ -500,3 +503,94 @@ def fit_power_rate(P, r):
     A = np.stack([np.asarray(P, dtype=np.float64), np.ones(len(P))], axis=1)
     sol, *_ = np.linalg.lstsq(A, np.asarray(r, dtype=np.float64), rcond=None)
     return float(sol[0]), float(sol[1])
+
+
+# ---------------------------------------------------------------------------------------------
+# Tilt inversion (Results, cathode-tilt study, Figure 8).  The simulation is repeated over a
+# sweep of one geometry parameter (the common cathode tilt); each sweep point gives a library of
+# compositions, which is compared with a measured one through the compositional area it covers
+# and through d_e.
+# ---------------------------------------------------------------------------------------------
+def sweep_composition(f, a, b, P, M, rho):
+    """at.% [T, J, K] of T libraries made with the same powers P [K]: f [T, K, J] holds the
+    area values of each sweep point, and each library is normalised by its own calibration
+    value (the mean of its areas, as in ``composition``)."""
+    f = np.asarray(f, dtype=np.float64)
+    P = np.asarray(P, dtype=np.float64)[None, :]
+    return np.stack([composition(f[t], a, b, P, M, rho, f[t].mean(axis=1))[0] for t in range(f.shape[0])])
+
+
+def ternary_xy(c):
+    """Coordinates in the ternary composition diagram: the pure elements 0, 1, 2 sit at the
+    corners (0, 0), (100, 0), (50, 50 sqrt 3) of an equilateral triangle of side 100, so a
+    composition (c0, c1, c2) in at.% maps to x = c1 + c2 / 2, y = c2 sqrt(3) / 2."""
+    c = np.asarray(c, dtype=np.float64)
+    return c[:, 1] + 0.5 * c[:, 2], c[:, 2] * (math.sqrt(3.0) / 2.0)
+
+
+def _cross(o, a, b):
+    return (a[0] - o[0]) * (b[1] - o[1]) - (a[1] - o[1]) * (b[0] - o[0])
+
+
+def hull_area_fraction(c):
+    """Compositional area a ternary library covers: the area of the convex hull of its
+    compositions c [J, 3] in the ternary diagram, as a fraction of the whole diagram.
+
+    The hull is Andrew's monotone chain (points sorted by x, then y; a point is dropped while
+    it does not make a strict left turn), the area the shoelace sum over the hull in that
+    order (lower chain from the leftmost point, then the upper chain back)."""
+    x, y = ternary_xy(c)
+    pts = sorted(zip(x.tolist(), y.tolist()))
+    if len(pts) < 3:
+        return 0.0
+    lower, upper = [], []
+    for p in pts:
+        while len(lower) >= 2 and _cross(lower[-2], lower[-1], p) <= 0.0:
+            lower.pop()
+        lower.append(p)
+    for p in reversed(pts):
+        while len(upper) >= 2 and _cross(upper[-2], upper[-1], p) <= 0.0:
+            upper.pop()
+        upper.append(p)
+    hull = lower[:-1] + upper[:-1]
+    s = 0.0
+    for i in range(len(hull)):
+        xa, ya = hull[i]
+        xb, yb = hull[(i + 1) % len(hull)]
+        s += xa * yb - xb * ya
+    return 0.5 * s / (math.sqrt(3.0) / 4.0 * 100.0 * 100.0)
+
+
+def sweep_fit_min(x, y):
+    """Sweep parameter that minimises y (samples at strictly increasing x): the smallest sample
+    (the first on ties), refined by the vertex of the parabola through it and its two
+    neighbours, kept inside their bracket; at either end of the sweep, that end."""
+    x = [float(v) for v in x]
+    y = [float(v) for v in y]
+    i = min(range(len(y)), key=lambda t: (y[t], t))
+    if i == 0 or i == len(y) - 1:
+        return x[i]
+    x0, x1, x2 = x[i - 1], x[i], x[i + 1]
+    y0, y1, y2 = y[i - 1], y[i], y[i + 1]
+    num = (x1 - x0) ** 2 * (y1 - y2) - (x1 - x2) ** 2 * (y1 - y0)
+    den = (x1 - x0) * (y1 - y2) - (x1 - x2) * (y1 - y0)
+    if den == 0.0:
+        return x1
+    return min(max(x1 - 0.5 * num / den, x0), x2)
+
+
+def sweep_fit_match(x, y, target):
+    """Sweep parameter at which y reaches ``target``: linear interpolation inside the first
+    pair of neighbouring samples that bracket it (a sample equal to it is returned as is);
+    NaN if no pair brackets it."""
+    x = [float(v) for v in x]
+    y = [float(v) for v in y]
+    target = float(target)
+    for t in range(len(y) - 1):
+        if y[t] == target:
+            return x[t]
+        if (y[t] - target) * (y[t + 1] - target) < 0.0:
+            return x[t] + (target - y[t]) * (x[t + 1] - x[t]) / (y[t + 1] - y[t])
+    if y and y[-1] == target:
+        return x[-1]
+    return math.nan

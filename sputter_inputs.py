@@ -250,6 +250,44 @@ def quaternary_sweep(n_configs: int = 64, seed: int = 0, scale: float = 1.0) -> 
 
 
 # ---------------------------------------------------------------------------
+# Ternary Pd-Pt-Ru library and a sweep of the common cathode tilt (Results, the
+# cathode-tilt study).  The three cathodes take positions 1-3 of the four-cathode
+# ring; 200 mm keeps 50.8 mm targets clear of each other at tilts near 12 deg.
+# ---------------------------------------------------------------------------
+TERNARY_ELEMENTS = ("Pd", "Pt", "Ru")
+TERNARY_POWERS = (40.0, 18.0, 35.0)          # W, the Pd-Pt-Ru library of Table 1 (Pd on RF)
+# Sputter rate = a P + b (nm/s per W, nm/s): the lines through the two calibration samples of
+# Table S1 for each element and supply (Pd RF 7 / 60 W, Pt DC 5 / 35 W, Ru DC 5 / 35 W).
+TERNARY_RATE_A = (0.0013669622641509437, 0.003086333333333334, 0.0014952666666666666)
+TERNARY_RATE_B = (-0.004707735849056604, -0.001321666666666701, -0.002054333333333349)
+TERNARY_DISTANCE = 200.0
+
+
+def ternary(pressure: float = 0.5, tilt_deg: float = 12.2, distance: float = TERNARY_DISTANCE,
+            n_particles: int = 1_000_000, grid_n: int = 200) -> Config:
+    """Pd, Pt, Ru on confocal cathodes 1-3 (azimuths 90, 180, 270 deg), each launching
+    ``n_particles``, onto the 100 mm wafer."""
+    cats = [_confocal_cathode(el, k + 1, tilt_deg, distance, int(n_particles))
+            for k, el in enumerate(TERNARY_ELEMENTS)]
+    grid = Grid(center=(0.0, 0.0, WAFER_Z), normal=(0.0, 0.0, -1.0), u_axis=(1.0, 0.0, 0.0),
+                half_u=50.0, half_v=50.0, shape=1, nu=grid_n, nv=grid_n)
+    return Config(chamber=Chamber(pressure=pressure), grid=grid, cathodes=cats)
+
+
+def tilt_sweep(tilts: Sequence[float], pressure: float = 0.5, distance: float = TERNARY_DISTANCE,
+               n_particles: int = 1_000_000) -> List[Config]:
+    """One ternary configuration per tilt (the sweep of one launch)."""
+    return [ternary(pressure, float(t), distance, n_particles) for t in tilts]
+
+
+def ternary_composition_inputs():
+    """(a, b, P, M, rho) of the ternary library, float64 arrays of 3."""
+    M = np.array([SPECIES[e]["mass"] for e in TERNARY_ELEMENTS])
+    rho = np.array([SPECIES[e]["density"] for e in TERNARY_ELEMENTS])
+    return (np.array(TERNARY_RATE_A), np.array(TERNARY_RATE_B), np.array(TERNARY_POWERS), M, rho)
+
+
+# ---------------------------------------------------------------------------
 # Composition-map inputs: linear power-rate model and a batch of power vectors.
 # ---------------------------------------------------------------------------
 @dataclass
