@@ -79,6 +79,10 @@ def algorithmic_ops(counters):
             float(diffusive_steps * OPS["DIFFUSIVE"]))
 
 
+TILT_SWEEP = [11.0, 11.5, 12.0, 12.5, 13.0, 13.5, 14.0, 14.5]
+TILT_PLANTED = 12.7
+
+
 def workload(name, scale=1.0):
     import sputter_inputs as si
     if name == "legs":
@@ -100,6 +104,13 @@ def workload(name, scale=1.0):
         cfg = si.with_chimneys(si.quaternary())
         return [cfg], ("four confocal cathodes Ni/Pd/Pt/Ru, tilt 25 deg, 150 mm, Ar 0.5 Pa, 100 mm wafer 200x200 bins, "
                        "2.3e7 particles; each target in a 30 mm open chimney (radius + 5 mm), the other targets absorb")
+    if name == "tilt_fit":
+        n = int(1e8 * scale)
+        return (si.tilt_sweep(TILT_SWEEP, n_particles=n),
+                f"tilt inversion of a ternary Pd-Pt-Ru library: {len(TILT_SWEEP)} common cathode tilts "
+                f"{TILT_SWEEP[0]}-{TILT_SWEEP[-1]} deg x 3 confocal cathodes (200 mm) x {n:.0e} particles at "
+                f"Ar 0.5 Pa in one launch, then 342 areas, at.%, d_e^2 and covered area against a library "
+                f"simulated at {TILT_PLANTED} deg, and both fits")
     if name == "sweep":
         cfgs = si.quaternary_sweep(64, scale=scale)
         return cfgs, "64 four-cathode chambers: p U(0.1,2) Pa, tilt U(0,40) deg, distance U(80,200) mm, 1e5-1e7 particles each"
@@ -116,10 +127,12 @@ def tally_error(counts_seg):
     return vals
 
 
-def time_steps(plan, bufs, seed, steps, warmup, phase_times=True):
+def time_steps(plan, bufs, seed, steps, warmup, phase_times=True, post=None):
     import torch
     for _ in range(warmup):
         plan.run_into(seed, bufs)
+        if post is not None:
+            post(bufs)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
@@ -129,6 +142,8 @@ def time_steps(plan, bufs, seed, steps, warmup, phase_times=True):
     for a, b in ev:
         a.record(stream)
         plan.run_into(seed, bufs)
+        if post is not None:
+            post(bufs)
         b.record(stream)
         # per-kernel device times of this step, from the HIP events the plan records between
         # its kernels on this stream (waits for the step: a few microseconds per step)
@@ -162,7 +177,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="legs", choices=["legs", "legs_measured", "quaternary", "quaternary_chimneys", "sweep"])
+    ap.add_argument("--workload", default="legs", choices=["legs", "legs_measured", "quaternary", "quaternary_chimneys", "sweep", "tilt_fit"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparator leg")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -209,7 +224,21 @@ def main():
         launch = plan.launch if args.no_autotune else plan.autotune()
     tune_s = time.perf_counter() - t
     bufs = plan.allocate(profiles=True, arrivals=args.arrivals)
-    wall, ms, phases = time_steps(plan, bufs, args.seed, args.steps, args.warmup)
+    post, inversion = None, None
+    if args.workload == "tilt_fit":
+        # the measured library: the same ternary system simulated at the planted tilt with other
+        # random numbers (set-up, not timed); the timed step is the sweep plus the inversion
+        n = cfgs[0].cathodes[0].n_particles
+        mplan = spx.Plan(si.tilt_sweep([TILT_PLANTED], n_particles=n), params)
+        mout = mplan.run(seed=args.seed + 1000)
+        cen = torch.as_tensor(spx.area_centres(), device="cuda")
+        comp = [torch.as_tensor(v, device="cuda") for v in si.ternary_composition_inputs()]
+        f_m = spx.area_gather(torch.stack(mout["profiles_seg"]), cfgs[0].grid, cen).view(1, 3, -1)
+        c_m = spx.sweep_composition(f_m, *comp)[0]
+        del mplan, mout
+        inversion = {}
+        post = lambda b: inversion.update(spx.invert_sweep(plan, b, TILT_SWEEP, comp, c_m, centres=cen))
+    wall, ms, phases = time_steps(plan, bufs, args.seed, args.steps, args.warmup, post=post)
     counters = bufs["counters"].view(plan.n_segments, spx._native.N_COUNTERS).cpu().numpy().astype(np.float64)
     n_part = float(counters[:, 0].sum())
     assert n_part == plan.n_particles
@@ -251,6 +280,24 @@ def main():
         "setup_s": {"plan_and_table": setup_s, "autotune": tune_s},
         "roofline": roofline,
     }
+
+    if inversion is not None:
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(10):
+            post(bufs)
+        ev[1].record()
+        torch.cuda.synchronize()
+        result["inversion"] = {
+            "tilts_deg": TILT_SWEEP, "planted_deg": TILT_PLANTED,
+            "fit_d_e_deg": float(inversion["x_min_de"].cpu()[0]),
+            "fit_covered_area_deg": float(inversion["x_match_area"].cpu()[0]),
+            "covered_area": [round(float(v), 6) for v in inversion["area"].cpu()],
+            "covered_area_measured": float(inversion["area_measured"].cpu()[0]),
+            "d_e2": [round(float(v), 3) for v in inversion["loss"].cpu()],
+            "chain_ms": ev[0].elapsed_time(ev[1]) / 10,
+            "note": "chain = area gather, sweep compositions, d_e^2, covered areas and both fits, after the "
+                    "transport (inside the timed step)"}
 
     if not args.no_fp64:
         plan64 = spx.Plan(cfgs, params, precision=64)

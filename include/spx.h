@@ -272,7 +272,7 @@ int spx_area_gather(const double* d_profiles, int32_t n_prof, int32_t nu, int32_
 /* Composition map, FP32 (Methods, conversion of arrival fractions to at.%):
  *   w[b,k]   = (a[k] P[b,k] + bb[k]) rho[k] / (M[k] fref[k])
  *   c[b,j,k] = 100 w[b,k] f[k,j] / sum_l w[b,l] f[l,j]
- * f [K,J] arrival fraction per area, P [B,K], a/bb/M/rho/fref [K], c [B,J,K]; K <= 64. */
+ * f [K,J] arrival fraction per area, P [B,K], a/bb/M/rho/fref [K], c [B,J,K]; 0 < K <= 16. */
 int spx_comp_forward(const float* d_f, const float* d_a, const float* d_b, const float* d_P,
                      const float* d_M, const float* d_rho, const float* d_fref, float* d_c,
                      int32_t B, int32_t J, int32_t K, void* stream);
@@ -291,6 +291,50 @@ int spx_comp_backward(const float* d_f, const float* d_a, const float* d_b, cons
  * (d_gloss nullable = all ones): gc = 2 (c - ct) gloss[b]. */
 int spx_comp_sqdist(const float* d_c, const float* d_ct, int32_t B_t, const float* d_gloss, float* d_loss,
                     float* d_gc, int32_t B, int32_t J, int32_t K, void* stream);
+
+/* ---- Inversion of a geometry parameter over a sweep (Results, the cathode-tilt study and
+ * Figure 8: the simulation is repeated over a range of cathode tilts and each simulated library
+ * is compared with the measured one by the compositional area it covers and by d_e). ---- */
+
+/* Compositions of the T libraries of a sweep, all made with the same powers, each normalised
+ * by its own calibration value fref[t,k] = mean over j of f[t,k,j] (the default of the
+ * composition map):
+ *   w[t,k] = (a[k] P[k] + bb[k]) rho[k] / (M[k] fref[t,k]),
+ *   c[t,j,k] = 100 w[t,k] f[t,k,j] / sum_l w[t,l] f[t,l,j].
+ * d_f double[T][K][J]: the area values of the K segments of each sweep point, as
+ * spx_area_gather writes them for T*K profiles of one grid; d_a, d_b, d_P, d_M, d_rho
+ * double[K]; d_c float[T][J][K] (written).  Computed in double, stored as float.
+ * Rejects T <= 0, J <= 0, K outside 1..16, null pointers (SPX_EINVAL). */
+int spx_sweep_composition(const double* d_f, const double* d_a, const double* d_b, const double* d_P,
+                          const double* d_M, const double* d_rho, float* d_c, int32_t T, int32_t J, int32_t K,
+                          void* stream);
+
+/* Compositional area covered by each of B ternary libraries: the area of the convex hull of
+ * its J compositions in the ternary diagram, as a fraction of the whole diagram.  The pure
+ * elements 0, 1, 2 sit at (0, 0), (100, 0), (50, 50 sqrt 3), so c (at.%) maps to
+ * x = c1 + c2/2, y = c2 sqrt(3)/2.  The hull is Andrew's monotone chain over the points
+ * sorted by (x, y), in double precision; a point that does not make a strict left turn is
+ * dropped; fewer than three points cover 0.  d_c float[B][J][3], d_area float[B] (written).
+ * Rejects B <= 0, J outside 1..2048, null pointers (SPX_EINVAL). */
+int spx_hull_area(const float* d_c, int32_t B, int32_t J, float* d_area, void* stream);
+
+#define SPX_FIT_MIN 0    /* the sweep value that minimises the curve */
+#define SPX_FIT_MATCH 1  /* the sweep value at which the curve reaches a target */
+
+/* Fit of one parameter over a sweep.  h_x: host double[T], the sweep values, finite and
+ * strictly increasing (copied into the launch); d_y float[B][T], one curve per row;
+ * d_xfit double[B] (written).
+ *   SPX_FIT_MIN:   the vertex of the least-squares parabola through all samples, kept inside
+ *                  the sweep, if it opens upwards; otherwise, or with fewer than three
+ *                  samples, the sweep value of the smallest sample (the first on ties).
+ *   SPX_FIT_MATCH: the sweep value at which the least-squares line through all samples
+ *                  reaches d_target[b] (device float[B]); NaN if that lies outside the sweep,
+ *                  if the line is flat, or with fewer than two samples.
+ * Least squares over the whole sweep average the Monte Carlo noise of the sweep points.
+ * Computed in double (sweep values scaled to [-1, 1], curves centred on their mean).  Rejects B <= 0, T outside 1..256, x not strictly increasing, an
+ * unknown mode, SPX_FIT_MATCH without targets, null pointers (SPX_EINVAL). */
+int spx_sweep_fit(const double* h_x, const float* d_y, int32_t B, int32_t T, int32_t mode, const float* d_target,
+                  double* d_xfit, void* stream);
 
 void spx_plan_destroy(spx_plan* plan);
 

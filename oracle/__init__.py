@@ -561,36 +561,45 @@ def hull_area_fraction(c):
     return 0.5 * s / (math.sqrt(3.0) / 4.0 * 100.0 * 100.0)
 
 
+def _sweep_coords(x):
+    """Sweep values as u = (x - mean) / half-range, in [-1, 1]."""
+    x = np.asarray(x, dtype=np.float64)
+    xm = float(x.mean())
+    h = 0.5 * float(x[-1] - x[0])
+    return x, xm, h, (x - xm) / h
+
+
 def sweep_fit_min(x, y):
-    """Sweep parameter that minimises y (samples at strictly increasing x): the smallest sample
-    (the first on ties), refined by the vertex of the parabola through it and its two
-    neighbours, kept inside their bracket; at either end of the sweep, that end."""
-    x = [float(v) for v in x]
-    y = [float(v) for v in y]
+    """Sweep parameter that minimises a misfit y sampled at strictly increasing x: the vertex
+    of the least-squares parabola through all samples, kept inside the sweep, if the parabola
+    opens upwards; otherwise (or with fewer than three samples) the x of the smallest sample,
+    the first on ties."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
     i = min(range(len(y)), key=lambda t: (y[t], t))
-    if i == 0 or i == len(y) - 1:
-        return x[i]
-    x0, x1, x2 = x[i - 1], x[i], x[i + 1]
-    y0, y1, y2 = y[i - 1], y[i], y[i + 1]
-    num = (x1 - x0) ** 2 * (y1 - y2) - (x1 - x2) ** 2 * (y1 - y0)
-    den = (x1 - x0) * (y1 - y2) - (x1 - x2) * (y1 - y0)
-    if den == 0.0:
-        return x1
-    return min(max(x1 - 0.5 * num / den, x0), x2)
+    if len(x) < 3:
+        return float(x[i])
+    x, xm, h, u = _sweep_coords(x)
+    A = np.stack([np.ones_like(u), u, u * u], axis=1)
+    p = np.linalg.lstsq(A, y - y.mean(), rcond=None)[0]      # centred: a flat curve fits exactly 0
+    if not p[2] > 0.0:
+        return float(x[i])
+    return float(min(max(xm - h * p[1] / (2.0 * p[2]), x[0]), x[-1]))
 
 
 def sweep_fit_match(x, y, target):
-    """Sweep parameter at which y reaches ``target``: linear interpolation inside the first
-    pair of neighbouring samples that bracket it (a sample equal to it is returned as is);
-    NaN if no pair brackets it."""
-    x = [float(v) for v in x]
-    y = [float(v) for v in y]
-    target = float(target)
-    for t in range(len(y) - 1):
-        if y[t] == target:
-            return x[t]
-        if (y[t] - target) * (y[t + 1] - target) < 0.0:
-            return x[t] + (target - y[t]) * (x[t + 1] - x[t]) / (y[t + 1] - y[t])
-    if y and y[-1] == target:
-        return x[-1]
-    return math.nan
+    """Sweep parameter at which a curve y sampled at strictly increasing x reaches ``target``:
+    where the least-squares line through all samples reaches it; NaN if that lies outside the
+    sweep, if the line is flat, or with fewer than two samples."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    if len(x) < 2:
+        return math.nan
+    x, xm, h, u = _sweep_coords(x)
+    ym = float(y.mean())
+    uc = u - u.mean()
+    q1 = float((uc * (y - ym)).sum() / (uc * uc).sum())      # slope of the least-squares line
+    if q1 == 0.0:
+        return math.nan
+    v = xm + h * (u.mean() + (float(target) - ym) / q1)
+    return float(v) if x[0] <= v <= x[-1] else math.nan

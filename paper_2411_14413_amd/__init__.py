@@ -276,7 +276,8 @@ def area_gather(profiles, grid, centres, half_width: float = 2.25, stream=None):
     p = profiles.contiguous()
     if p.dim() == 2:
         p = p.unsqueeze(0)
-    cen = torch.as_tensor(np.asarray(centres, dtype=np.float64), device=p.device).contiguous()
+    cen = (centres.to(device=p.device, dtype=torch.float64).contiguous() if isinstance(centres, torch.Tensor)
+           else torch.as_tensor(np.asarray(centres, dtype=np.float64), device=p.device).contiguous())
     out = torch.empty(p.shape[0], cen.shape[0], dtype=torch.float64, device=p.device)
     check(lib().spx_area_gather(_ptr(p), p.shape[0], int(grid.nu), int(grid.nv), float(grid.half_u),
                                 float(grid.half_v), _ptr(cen), cen.shape[0], float(half_width), _ptr(out),
@@ -324,6 +325,89 @@ def comp_sqdist(c, ct, gloss=None, want_grad: bool = False, stream=None):
     check(lib().spx_comp_sqdist(_ptr(c), _ptr(ct), ct.shape[0], _ptr(gl), _ptr(loss), _ptr(gc), B, J, K,
                                 _stream(stream)), "spx_comp_sqdist")
     return (loss, gc) if want_grad else loss
+
+
+# -- inversion over a sweep (Results, cathode-tilt study) --------------------------------------
+FIT_MIN, FIT_MATCH = 0, 1
+
+
+def _f64(t):
+    return t.detach().contiguous().double() if t.dtype != _torch().float64 else t.detach().contiguous()
+
+
+def sweep_composition(f, a, b, P, M, rho, stream=None):
+    """at.% [T, J, K] (float32) of the T libraries of a sweep: f [T, K, J] float64 area values
+    (each library normalised by the mean of its own areas); a, b, P, M, rho [K]."""
+    torch = _torch()
+    f = _f64(f)
+    dev = f.device
+    a, b, P, M, rho = (_f64(torch.as_tensor(np.asarray(v, dtype=np.float64), device=dev)) if not
+                       isinstance(v, torch.Tensor) else _f64(v) for v in (a, b, P, M, rho))
+    T, K, J = f.shape
+    c = torch.empty(T, J, K, dtype=torch.float32, device=dev)
+    check(lib().spx_sweep_composition(_ptr(f), _ptr(a), _ptr(b), _ptr(P), _ptr(M), _ptr(rho), _ptr(c), T, J, K,
+                                      _stream(stream)), "spx_sweep_composition")
+    return c
+
+
+def hull_area(c, stream=None):
+    """Covered fraction of the ternary diagram [B] (float32) of libraries c [B, J, 3] or [J, 3]."""
+    torch = _torch()
+    c = _f32(c)
+    if c.dim() == 2:
+        c = c.unsqueeze(0)
+    if c.shape[2] != 3:
+        raise ValueError("hull_area needs ternary compositions [B, J, 3]")
+    out = torch.empty(c.shape[0], dtype=torch.float32, device=c.device)
+    check(lib().spx_hull_area(_ptr(c), c.shape[0], c.shape[1], _ptr(out), _stream(stream)), "spx_hull_area")
+    return out
+
+
+def sweep_fit(x, y, mode: int, target=None, stream=None):
+    """Fitted sweep values [B] (float64): y [B, T] or [T] float32 curves over the host sweep
+    values x [T]; mode FIT_MIN (minimiser) or FIT_MATCH (where y reaches target [B])."""
+    torch = _torch()
+    y = _f32(y)
+    if y.dim() == 1:
+        y = y.unsqueeze(0)
+    hx = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if hx.shape != (y.shape[1],):
+        raise ValueError("sweep_fit: x must have one value per column of y")
+    tg = _f32(target).reshape(-1) if target is not None else None
+    out = torch.empty(y.shape[0], dtype=torch.float64, device=y.device)
+    check(lib().spx_sweep_fit(hx.ctypes.data_as(ctypes.c_void_p), _ptr(y), y.shape[0], y.shape[1], int(mode),
+                              _ptr(tg), _ptr(out), _stream(stream)), "spx_sweep_fit")
+    return out
+
+
+def invert_sweep(plan, out, x, comp, measured, centres=None, half_width: float = 2.25, stream=None):
+    """Finish the inversion of a sweep run: ``plan`` holds one configuration per sweep value
+    x [T] (same grid, K cathodes each) and ``out`` its run with profiles; ``comp`` = (a, b, P,
+    M, rho) of the library; ``measured`` the measured compositions [J, K] (CUDA); ``centres``
+    the area centres [J, 2] (numpy or CUDA; default the 342 areas).  Every step is
+    a library call: area gather, compositions, d_e^2 against the measured library, covered
+    areas (K = 3) and the two fits."""
+    torch = _torch()
+    T = len(x)
+    K = plan.n_segments // T
+    nv, nu = plan.shapes[0]
+    if K * T != plan.n_segments or any(o != k * nv * nu for k, o in enumerate(plan.bin_off)) or \
+            any(sh != (nv, nu) for sh in plan.shapes):
+        raise ValueError("invert_sweep: the plan must hold T configurations of K cathodes on one grid")
+    grid = plan.configs[0].grid
+    cen = area_centres() if centres is None else centres
+    prof = out["profiles"][:plan.n_segments * nv * nu].view(plan.n_segments, nv, nu)
+    f = area_gather(prof, grid, cen, half_width, stream).view(T, K, -1)
+    c = sweep_composition(f, *comp, stream=stream)
+    meas = _f32(measured).reshape(1, c.shape[1], K)
+    loss = comp_sqdist(c, meas, stream=stream)
+    res = dict(f=f, c=c, loss=loss, x_min_de=sweep_fit(x, loss, FIT_MIN, stream=stream))
+    if K == 3:
+        area = hull_area(c, stream)
+        area_m = hull_area(meas, stream)
+        res.update(area=area, area_measured=area_m,
+                   x_match_area=sweep_fit(x, area, FIT_MATCH, target=area_m, stream=stream))
+    return res
 
 
 def _autograd_classes():

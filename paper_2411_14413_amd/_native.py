@@ -104,6 +104,9 @@ SIGNATURES = {
     "spx_comp_forward": (ctypes.c_int, [_vp] * 8 + [_i32, _i32, _i32, _vp]),
     "spx_comp_backward": (ctypes.c_int, [_vp] * 15 + [_i32, _i32, _i32, _vp]),
     "spx_comp_sqdist": (ctypes.c_int, [_vp, _vp, _i32, _vp, _vp, _vp, _i32, _i32, _i32, _vp]),
+    "spx_sweep_composition": (ctypes.c_int, [_vp] * 7 + [_i32, _i32, _i32, _vp]),
+    "spx_hull_area": (ctypes.c_int, [_vp, _i32, _i32, _vp, _vp]),
+    "spx_sweep_fit": (ctypes.c_int, [_vp, _vp, _i32, _i32, _i32, _vp, _vp, _vp]),
     "spx_plan_destroy": (None, [_vp]),
     "spx_last_error": (ctypes.c_char_p, []),
     "spx_version": (ctypes.c_int32, []),

@@ -127,3 +127,24 @@ def test_valid_config_without_device_is_a_device_error():
     with pytest.raises(SpxError) as e:
         _create([si.single_ni(0.5, 10)])
     assert e.value.code == -3
+
+
+def test_inversion_entry_points_reject_bad_arguments():
+    """Host-side checks of the inversion calls, before any device work."""
+    from paper_2411_14413_amd._native import lib, SPX_EINVAL
+    L = lib()
+    fake = ctypes.c_void_p(256)
+    x = (ctypes.c_double * 4)(11.0, 12.0, 13.0, 14.0)
+    xbad = (ctypes.c_double * 4)(11.0, 13.0, 12.0, 14.0)
+    assert L.spx_sweep_composition(fake, fake, fake, fake, fake, fake, fake, 2, 342, 17, None) == SPX_EINVAL
+    assert L.spx_sweep_composition(fake, fake, fake, fake, fake, fake, None, 2, 342, 3, None) == SPX_EINVAL
+    assert L.spx_sweep_composition(fake, fake, fake, fake, fake, fake, fake, 0, 342, 3, None) == SPX_EINVAL
+    assert L.spx_hull_area(fake, 1, 2049, fake, None) == SPX_EINVAL
+    assert L.spx_hull_area(fake, 0, 342, fake, None) == SPX_EINVAL
+    assert L.spx_hull_area(None, 1, 342, fake, None) == SPX_EINVAL
+    assert L.spx_sweep_fit(xbad, fake, 1, 4, 0, None, fake, None) == SPX_EINVAL
+    assert b"increasing" in L.spx_last_error()
+    assert L.spx_sweep_fit(x, fake, 1, 4, 7, None, fake, None) == SPX_EINVAL
+    assert L.spx_sweep_fit(x, fake, 1, 4, 1, None, fake, None) == SPX_EINVAL
+    assert L.spx_sweep_fit(x, fake, 1, 300, 0, None, fake, None) == SPX_EINVAL
+    assert L.spx_sweep_fit(None, fake, 1, 4, 0, None, fake, None) == SPX_EINVAL

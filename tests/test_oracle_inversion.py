@@ -9,8 +9,11 @@ compositional area it covers and by d_e).
   area does not depend on point order or on which element is called 0, 1, 2 (the diagram map
   is an isometry of the simplex); random small sets against a brute-force sum over the hull
   edges found by the all-points-on-one-side test.
-* Fits: a sampled parabola gives its vertex on uneven sweeps; a minimum at an end gives that
-  end; a sampled line gives its exact crossing; no bracket gives NaN.
+* Fits: a sampled parabola gives its vertex on uneven sweeps, unmoved by an offset or scale of
+  the misfit and shifted with the sweep; a vertex outside the sweep gives its end; a parabola
+  opening downwards or a flat one gives the smallest sample; on noisy samples the vertex is
+  unbiased; a sampled line gives its exact crossing, also with residuals orthogonal to lines
+  added; a crossing outside the sweep or a flat line gives NaN.
 * Sweep compositions: each library sums to 100 at.% at every area, is unchanged when its area
   values are scaled, and a lone element is 100 at.%.
 * The ternary library's rate lines are the least-squares lines through Table S1's samples.
@@ -121,30 +124,44 @@ def test_against_brute_force(n):
 def test_fit_min_parabola_vertex():
     rng = np.random.default_rng(5)
     for _ in range(50):
-        x = np.sort(rng.uniform(10, 16, 9))
-        x0 = rng.uniform(x[1], x[-2])
-        y = 3.0 * (x - x0) ** 2 + 7.0
-        i = int(np.argmin(y))
-        if i in (0, len(x) - 1):
-            continue
+        x = np.sort(rng.uniform(10, 16, int(rng.integers(3, 12))))
+        x0 = rng.uniform(x[0], x[-1])
+        y = rng.uniform(0.1, 5.0) * (x - x0) ** 2 + rng.uniform(-3, 3)
         assert abs(oracle.sweep_fit_min(x, y) - x0) < 1e-9
+        # a constant or a positive scale of the misfit, or a shift of the sweep, moves nothing
+        assert abs(oracle.sweep_fit_min(x, 3.0 * y + 10.0) - x0) < 1e-9
+        assert abs(oracle.sweep_fit_min(x + 2.5, y) - (x0 + 2.5)) < 1e-9
     x = np.linspace(11, 14, 7)
-    assert oracle.sweep_fit_min(x, (x - 10.0) ** 2) == 11.0
-    assert oracle.sweep_fit_min(x, -(x - 10.0)) == 14.0
-    assert oracle.sweep_fit_min(x, np.ones(7)) == 11.0
-    y = np.array([5.0, 1.0, 1.0, 5.0, 6.0, 7.0, 8.0])      # tie: the first minimum, refined
-    assert 11.0 <= oracle.sweep_fit_min(x, y) <= 12.0
+    assert oracle.sweep_fit_min(x, (x - 9.0) ** 2) == 11.0          # vertex left of the sweep
+    assert oracle.sweep_fit_min(x, (x - 16.0) ** 2) == 14.0         # right of it
+    assert oracle.sweep_fit_min(x, -(x - 12.0) ** 2) == 14.0        # opens downwards: smallest sample
+    assert oracle.sweep_fit_min(x, np.ones(7)) == 11.0              # flat: the first sample
+    assert oracle.sweep_fit_min(x[:2], [2.0, 1.0]) == x[1]
+
+
+def test_fit_min_averages_noise():
+    """Noise on the samples: the least-squares vertex scatters around the true one by about
+    sigma_v = sqrt(var), well inside the sample spacing, and without bias."""
+    rng = np.random.default_rng(8)
+    x = np.linspace(11.0, 14.5, 8)
+    x0 = 12.7
+    v = np.array([oracle.sweep_fit_min(x, 100.0 * (x - x0) ** 2 + rng.normal(0, 20.0, 8)) for _ in range(400)])
+    assert abs(v.mean() - x0) < 0.02 and v.std() < 0.1
 
 
 def test_fit_match_line_crossing():
+    rng = np.random.default_rng(9)
     x = np.array([11.0, 11.7, 12.1, 13.0, 14.2])
     for slope in (0.5, -0.8):
         y = slope * (x - 12.6) + 1.0
         assert abs(oracle.sweep_fit_match(x, y, 1.0) - 12.6) < 1e-12
-        assert math.isnan(oracle.sweep_fit_match(x, y, 1.0 + 10 * abs(slope)))
-    y = np.array([0.1, 0.2, 0.3, 0.4, 0.5])
-    assert oracle.sweep_fit_match(x, y, 0.3) == 12.1
-    assert oracle.sweep_fit_match(x, y, 0.5) == 14.2
+        assert math.isnan(oracle.sweep_fit_match(x, y, 1.0 + 10 * abs(slope)))      # outside the sweep
+    assert math.isnan(oracle.sweep_fit_match(x, np.full(5, 2.0), 2.0))               # flat
+    assert math.isnan(oracle.sweep_fit_match(x[:1], [1.0], 1.0))
+    # symmetric noise about a line does not move the crossing
+    e = rng.normal(0, 0.1, 5)
+    e -= np.polynomial.polynomial.polyval(x, np.polynomial.polynomial.polyfit(x, e, 1))
+    assert abs(oracle.sweep_fit_match(x, 0.5 * (x - 12.6) + 1.0 + e, 1.0) - 12.6) < 1e-12
 
 
 def test_sweep_composition_invariants():
