@@ -632,14 +632,15 @@ static int create(const spx_config* cfgs, int n_cfgs, const spx_params* prm, Pla
         release(P);
         return SPX_EDEVICE;
     }
-    int bpc = 0;
-    if (occupancy_transport32(P, P->threads, &bpc) != SPX_OK || bpc < 1) {
+    int bpc = 0, bpc_d = 0;
+    if (occupancy_transport32(P, P->threads, &bpc, &bpc_d) != SPX_OK || bpc < 1 || bpc_d < 1) {
         release(P);
-        set_error("occupancy query failed for the transport kernel");
+        set_error("occupancy query failed for the transport kernels");
         return SPX_EDEVICE;
     }
     P->max_blocks_per_cu = bpc;
     P->blocks = bpc * P->n_cu;
+    P->blocks_diff = std::min(P->blocks, bpc_d * P->n_cu);
     *out = P;
     return SPX_OK;
 }
@@ -719,7 +720,7 @@ static int run(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st)
         }
         SPX_HIP(hipStreamBeginCapture(P->work_stream, hipStreamCaptureModeThreadLocal));
         const int rc = launch_transport32(P, seed, o, P->work_stream, P->d_tfirst, P->n_tickets, P->blocks,
-                                          P->threads, P->refill_min, P->refill_ballistic, nullptr);
+                                          P->blocks_diff, P->threads, P->refill_min, P->refill_ballistic, nullptr);
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(P->work_stream, &g);
         if (rc != SPX_OK) {
@@ -750,8 +751,8 @@ static int autotune(Plan* P, hipStream_t st)
     // launch ends in a tail of the longest histories whose share of the time shrinks with the
     // work per lane, and a sample with too little work per lane favours shapes that only
     // shorten that tail.
-    int bpc_max = 0;
-    SPX_TRY(occupancy_transport32(P, 256, &bpc_max));
+    int bpc_max = 0, bpc_dmax = 0;
+    SPX_TRY(occupancy_transport32(P, 256, &bpc_max, &bpc_dmax));
     const double lanes = (double)std::max(1, bpc_max) * P->n_cu * 256.0;
     const double frac =
         std::min(1.0, std::max(48.0 * lanes, 4e7) / (double)std::max<uint64_t>(1, P->n_particles_total));
@@ -773,22 +774,23 @@ static int autotune(Plan* P, hipStream_t st)
     if (rc == SPX_OK && hipMemcpyAsync(d_tf, tf.data(), sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess)
         rc = SPX_EDEVICE;
     float best = 1e30f;
-    int bb = P->blocks, bt = P->threads, br = P->refill_min, bm = P->refill_ballistic;
+    int bb = P->blocks, bd = P->blocks_diff, bt = P->threads, br = P->refill_min, bm = P->refill_ballistic;
     const int thread_opts[] = {256, 512, 1024};
     const int mode_opts[][2] = {{4, 4}, {4, 16}, {8, 8}};   // (refill_min, refill_ballistic)
     for (int t : thread_opts) {
         if (rc != SPX_OK) break;
-        int bpc = 0;
-        if (occupancy_transport32(P, t, &bpc) != SPX_OK || bpc < 1) continue;
+        int bpc = 0, bpc_d = 0;
+        if (occupancy_transport32(P, t, &bpc, &bpc_d) != SPX_OK || bpc < 1 || bpc_d < 1) continue;
         for (const auto& ro : mode_opts) {
-            const int blocks = bpc * P->n_cu;
+            const int blocks = bpc * P->n_cu, blocks_d = std::min(blocks, bpc_d * P->n_cu);
             float ms_min = 1e30f;
             for (int rep = 0; rep < 2 && rc == SPX_OK; ++rep) {
                 if (hipEventRecord(e0, st) != hipSuccess) rc = SPX_EDEVICE;
                 Outputs to;
                 to.counts = d_counts;
                 to.counters = d_ctr;
-                if (rc == SPX_OK) rc = launch_transport32(P, 0x5eed, to, st, d_tf, tf[n], blocks, t, ro[0], ro[1], nullptr);
+                if (rc == SPX_OK)
+                    rc = launch_transport32(P, 0x5eed, to, st, d_tf, tf[n], blocks, blocks_d, t, ro[0], ro[1], nullptr);
                 if (rc == SPX_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
                     rc = SPX_EDEVICE;
                 float ms = 0.f;
@@ -797,6 +799,7 @@ static int autotune(Plan* P, hipStream_t st)
             if (rc == SPX_OK && ms_min < best) {
                 best = ms_min;
                 bb = blocks;
+                bd = blocks_d;
                 bt = t;
                 br = ro[0];
                 bm = ro[1];
@@ -813,6 +816,7 @@ static int autotune(Plan* P, hipStream_t st)
         return rc;
     }
     P->blocks = bb;
+    P->blocks_diff = bd;
     P->threads = bt;
     P->refill_min = br;
     P->refill_ballistic = bm;
@@ -950,12 +954,14 @@ int spx_set_launch(spx_plan* P, int32_t blocks, int32_t threads, int32_t refill_
     if (threads < 64 || threads > 1024 || (threads & 63)) return fail("threads must be a multiple of 64 in [64, 1024]");
     if (refill_min < 1 || refill_min > 64) return fail("refill_min must be in [1, 64]");
     if (refill_ballistic < 1 || refill_ballistic > 64) return fail("refill_ballistic must be in [1, 64]");
-    int bpc = 0;
-    SPX_TRY(occupancy_transport32(P, threads, &bpc));
-    if (bpc < 1) return fail("transport kernel does not fit with this block size");
-    // a persistent grid larger than the resident limit would still be correct, but it is never useful
+    int bpc = 0, bpc_d = 0;
+    SPX_TRY(occupancy_transport32(P, threads, &bpc, &bpc_d));
+    if (bpc < 1 || bpc_d < 1) return fail("transport kernels do not fit with this block size");
+    // a persistent grid larger than the resident limit would still be correct, but it is never
+    // useful: each kernel runs at most its own resident grid
     const int limit = bpc * P->n_cu;
     P->blocks = (blocks <= 0 || blocks > limit) ? limit : blocks;
+    P->blocks_diff = std::min(P->blocks, bpc_d * P->n_cu);
     P->threads = threads;
     P->refill_min = refill_min;
     P->refill_ballistic = refill_ballistic;

@@ -538,10 +538,10 @@ __device__ __forceinline__ void collide(const SegDev<R>& s, const TabDev<R>& tb,
     }
 }
 
-// Isotropic direction and exponential step of a thermalised atom from its three 21-bit codes
-// (length, direction cosine, azimuth).
+// Isotropic direction and exponential step (mean lam_th, the segment's thermal mean free path)
+// of a thermalised atom from its three 21-bit codes (length, direction cosine, azimuth).
 template <typename R>
-__device__ __forceinline__ R diffusive_draw(const SegDev<R>& s, const uint32_t* k, R* d)
+__device__ __forceinline__ R diffusive_draw(R lam_th, const uint32_t* k, R* d)
 {
     const R u0 = u21<R>(k[0]), u1 = u21<R>(k[1]), u2 = u21<R>(k[2]);
     const R mu = (R)2 * u1 - (R)1;
@@ -551,7 +551,7 @@ __device__ __forceinline__ R diffusive_draw(const SegDev<R>& s, const uint32_t* 
     d[0] = st * cp;
     d[1] = st * sp;
     d[2] = mu;
-    return -s.lam_th * m_log(u0);
+    return -lam_th * m_log(u0);
 }
 
 // Compensated (Kahan) accumulation: the position is s - c with c the rounding lost so far,
@@ -605,7 +605,7 @@ __device__ __forceinline__ Term step_mode(const SegDev<R>& s, const TabDev<R>& t
     } else {
         uint32_t k[3];
         diffusive_codes(diffusive_block(pid, e, s.cfgcat, k0, k1), (e & 1u) != 0, k);
-        ell = diffusive_draw(s, k, p.d);   // diffusive only after a gas collision: never in vacuum
+        ell = diffusive_draw(s.lam_th, k, p.d);   // diffusive only after a gas collision: never in vacuum
     }
     R t, qu = (R)0, qv = (R)0;
     const HitF h = hit_test(s, p.x, p.d, ell, t, qu, qv, e == 1u);
@@ -675,65 +675,33 @@ __device__ __forceinline__ bool ball_holds(const float* t, const float* c, float
 // position and of the surface test at chamber sizes up to metres.
 constexpr float CLEAR_MARGIN = 0.02f;
 
-// One diffusive step of the batched FP32 path (event p.e + 1).  The direction is drawn
-// afresh every step, so in this mode p.d holds the centre of a clearance ball and p.r2 its
-// squared radius: the anchor's clearance less CLEAR_MARGIN.  A step that ends strictly
-// inside the ball (a convex set, entered at its start) stays more than CLEAR_MARGIN away
-// from every surface, so the surface test would find nothing and is skipped.  Otherwise the
-// step is tested as usual and, if it ends in the gas, the ball is rebuilt around its end.
-// Outcome and arithmetic are those of the tested step.
-__device__ __forceinline__ Term step_diffusive_ball(const SegDev<float>& s, uint32_t k0, uint32_t k1, uint32_t pid,
-                                                    uint32_t cap, Particle<float>& p)
-{
-    if (p.e >= cap) return Term{HIT_ESCAPED, -1, 0.f};
-    const uint32_t e = p.e + 1;
-    p.e = e;
-    uint32_t k[3];
-    diffusive_codes(diffusive_block(pid, e, s.cfgcat, k0, k1), (e & 1u) != 0, k);
-    float dir[3], v[3];
-    const float ell = diffusive_draw(s, k, dir);   // diffusive only after a gas collision
-    step_vector(ell, dir, v);
-    // the compensated move, not yet committed
-    float y[3], t[3];
-    kahan_try(p.x, p.xc, v, y, t);
-    const bool inside = ball_holds(t, p.d, p.r2);   // false for NaN / infinite steps
-    if (!inside) {
-        float th, qu = 0.f, qv = 0.f;
-        const HitF h = hit_test(s, p.x, dir, ell, th, qu, qv, false);
-        if (h.state != HIT_NONE) {
-#pragma unroll
-            for (int i = 0; i < 3; ++i) kahan_add(p.x[i], p.xc[i], th * dir[i]);
-            return hit_term(s, h.state, qu, qv, dir);
-        }
-        if (!(ell < m_inf<float>())) return Term{HIT_ESCAPED, -1, 0.f};
-    }
-    kahan_commit(p.x, p.xc, y, t);
-    ++p.ndiff;
-    if (!inside) {
-        const float c = clearance(s, p.x) - CLEAR_MARGIN;
-        p.d[0] = p.x[0]; p.d[1] = p.x[1]; p.d[2] = p.x[2];
-        p.r2 = c > 0.f ? c * c : -1.f;
-    }
-    return Term{HIT_NONE, -1, 0.f};
-}
-
-// The two halves of step_diffusive_ball for a wave that defers its surface tests.
+// A diffusive step of the batched FP32 path (event p.e + 1).  The direction is drawn afresh
+// every step, so in this mode p.d holds the centre of a clearance ball and p.r2 its squared
+// radius: the anchor's clearance less CLEAR_MARGIN.  A step that ends strictly inside the ball
+// (a convex set, entered at its start) stays more than CLEAR_MARGIN away from every surface,
+// so the surface test would find nothing and is skipped: the compensated move is committed.
+// Otherwise the step is tested as usual and, if it ends in the gas, the ball is rebuilt
+// around its end.  Outcome and arithmetic are those of the tested step.
+//
+// Such a step is taken in two halves, so that a wave can defer its surface tests.
 // diffusive_advance takes the next steps while they stay in the clearance ball: both steps
 // of the current Philox block (one if the next event is odd).  A step that leaves the ball
 // is held (direction in p.d, length in p.r2: the ball is rebuilt after the test anyway) and
-// sets held.  diffusive_resolve finishes a held step exactly as step_diffusive_ball would
-// have.  Steps, events and positions are those of step_diffusive_ball.
+// sets held.  diffusive_resolve tests a held step and finishes it.  The advance needs only
+// two numbers of the particle's segment (its thermal mean free path and the Philox counter
+// word), passed per lane, so lanes of different segments advance together; the test needs
+// the segment's geometry.
 //
 // One diffusive sub-step from block w (the odd or the even half) for a lane where `active`;
 // straight-line code ending in selects, so that inactive lanes keep their state and no
 // branch splits the wave.
-__device__ __forceinline__ void diffusive_substep(const SegDev<float>& s, uint4 w, bool odd, bool active,
-                                                  Particle<float>& p, bool& held)
+__device__ __forceinline__ void diffusive_substep(float lam_th, uint4 w, bool odd, bool active, Particle<float>& p,
+                                                  bool& held)
 {
     uint32_t k[3];
     diffusive_codes(w, odd, k);
     float dir[3], v[3];
-    const float ell = diffusive_draw(s, k, dir);   // diffusive only after a gas collision
+    const float ell = diffusive_draw(lam_th, k, dir);   // diffusive only after a gas collision
     step_vector(ell, dir, v);
     float y[3], t[3];
     kahan_try(p.x, p.xc, v, y, t);
@@ -753,15 +721,15 @@ __device__ __forceinline__ void diffusive_substep(const SegDev<float>& s, uint4 
     held = held || hold;
 }
 
-__device__ __forceinline__ Term diffusive_advance(const SegDev<float>& s, uint32_t k0, uint32_t k1, uint32_t pid,
-                                                  uint32_t cap, Particle<float>& p, bool& held)
+__device__ __forceinline__ Term diffusive_advance(float lam_th, uint32_t cfgcat, uint32_t k0, uint32_t k1,
+                                                  uint32_t pid, uint32_t cap, Particle<float>& p, bool& held)
 {
     if (p.e >= cap) return Term{HIT_ESCAPED, -1, 0.f};
-    const uint4 w = diffusive_block(pid, p.e + 1, s.cfgcat, k0, k1);
+    const uint4 w = diffusive_block(pid, p.e + 1, cfgcat, k0, k1);
     // the even step of the block (if the next event is even), then its odd step unless the
     // even one is held or the cap is reached (a capped history escapes at its next step)
-    diffusive_substep(s, w, false, ((p.e + 1) & 1u) == 0, p, held);
-    diffusive_substep(s, w, true, !held && p.e < cap, p, held);
+    diffusive_substep(lam_th, w, false, ((p.e + 1) & 1u) == 0, p, held);
+    diffusive_substep(lam_th, w, true, !held && p.e < cap, p, held);
     return Term{HIT_NONE, -1, 0.f};
 }
 
@@ -792,10 +760,10 @@ __device__ __forceinline__ Term diffusive_resolve(const SegDev<float>& s, Partic
 // draws step e + 1 + j (Philox block, direction, length, step vector), then the wave walks
 // the compensated sum through the drawn steps in order on wave-uniform values, stopping
 // before the first step that leaves the clearance ball or passes the event cap.  The sums
-// are those of step_diffusive_ball, operation for operation, so the committed position,
+// are those of diffusive_substep, operation for operation, so the committed position,
 // event and step counts equal those of taking the same steps one at a time; the step that
-// leaves the ball is left to step_diffusive_ball, which tests it.  Called by the whole
-// wave with L uniform.
+// leaves the ball is left to the regular walk, which holds and tests it.  Called by the
+// whole wave with L uniform.
 __device__ __forceinline__ void coop_walk(const SegDev<float>& s, uint32_t k0, uint32_t k1, uint32_t cap, uint32_t pid,
                                           Particle<float>& p, int L, int lane)
 {
@@ -814,7 +782,7 @@ __device__ __forceinline__ void coop_walk(const SegDev<float>& s, uint32_t k0, u
     uint32_t kc[3];
     diffusive_codes(diffusive_block(pidL, ej, s.cfgcat, k0, k1), (ej & 1u) != 0, kc);
     float dir[3], v[3];
-    const float ell = diffusive_draw(s, kc, dir);
+    const float ell = diffusive_draw(s.lam_th, kc, dir);
     step_vector(ell, dir, v);
     // steps that may be taken at all: within the event cap (the ball test rejects the rest)
     const uint64_t allowed = __ballot(ej <= cap);

@@ -169,6 +169,7 @@ struct spx_plan {
     uint64_t n_tickets = 0;
 
     int blocks = 0, threads = 256, refill_min = 8, refill_ballistic = 8;
+    int blocks_diff = 0;                    // grid of the diffusive kernel: blocks, capped at its resident limit
     int max_blocks_per_cu = 0, n_cu = 0;
 
     hipGraph_t graph = nullptr;
@@ -182,12 +183,13 @@ int build_tables(Plan* P);
 // events (nullable, not while capturing): 3 per round, recorded at the round's start, after
 // its ballistic phase and after its diffusive phase.
 int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st, const uint64_t* tfirst,
-                       uint64_t total, int blocks, int threads, int refill_min, int refill_ballistic,
+                       uint64_t total, int blocks, int blocks_diff, int threads, int refill_min, int refill_ballistic,
                        const hipEvent_t* events);
 uint64_t rounds_of(uint64_t total);
 bool is_ballistic_kernel(const void* f);
 int launch_transport64(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st);
 // Arrival bin edges in double (as the comparator uses them); the batched path rounds them to float.
 void arrival_edges(double* e_edges, double* c_edges);
-int occupancy_transport32(const Plan* P, int threads, int* blocks_per_cu);   // the smaller of the two kernels
+// resident blocks per CU of the ballistic and of the diffusive kernel at this block size
+int occupancy_transport32(const Plan* P, int threads, int* bpc_ballistic, int* bpc_diffusive);
 }  // namespace spx

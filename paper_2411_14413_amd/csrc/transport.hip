@@ -261,24 +261,42 @@ __device__ __forceinline__ void ballistic_loop(const TransportArgs& a, const Blo
 // steps are tested together, so the long test runs in few iterations.  No step is held
 // when the loop returns.
 template <bool ARR>
-__device__ __forceinline__ void diffusive_loop(const TransportArgs& a, const BlockTally& bt, const SegDev<float>& S,
-                                               uint32_t pid, Particle<float>& p, LaneAcc& acc, bool drained)
+__device__ __forceinline__ void diffusive_loop(const TransportArgs& a, const BlockTally& bt,
+                                               const SegDev<float>* __restrict__ segs, int seg, float lam_th,
+                                               uint32_t cfgcat, uint32_t pid, Particle<float>& p, LaneAcc& acc,
+                                               bool drained)
 {
     bool held = false;
     for (;;) {
-        if (p.st == ST_DIFFUSIVE && !held) {
-            const Term t = diffusive_advance(S, a.k0, a.k1, pid, a.cap, p, held);
-            if (t.state != HIT_NONE) terminate<ARR>(a, bt, S, pid, p, t, acc);
+        bool capped = false;
+        if (p.st == ST_DIFFUSIVE && !held)
+            capped = diffusive_advance(lam_th, cfgcat, a.k0, a.k1, pid, a.cap, p, held).state != HIT_NONE;
+        // histories at the event cap escape (rare): ended one segment at a time
+        for (uint64_t R = __ballot(capped); R != 0;) {
+            const int sL = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)R) - 1);
+            const bool mine = capped && seg == sL;
+            R &= ~__ballot(mine);
+            if (mine) {
+                capped = false;
+                terminate<ARR>(a, bt, segs[sL], pid, p, Term{HIT_ESCAPED, -1, 0.f}, acc);
+            }
         }
         const uint64_t H = __ballot(held);
         const uint64_t M = __ballot(p.st == ST_DIFFUSIVE);
         bool stop = M == 0 || (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) ||
                     (drained && __popcll(M) <= COOP_MAX);
         if (H != 0 && (stop || H == M || __popcll(H) >= DEFER_MIN)) {
-            if (held) {
-                held = false;
-                const Term t = diffusive_resolve(S, p);
-                if (t.state != HIT_NONE) terminate<ARR>(a, bt, S, pid, p, t, acc);
+            // the held steps, one segment at a time so that its geometry is read uniformly
+            for (uint64_t R = H; R != 0;) {
+                const int sL = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)R) - 1);
+                const bool mine = held && seg == sL;
+                R &= ~__ballot(mine);
+                if (mine) {
+                    held = false;
+                    const SegDev<float>& S = segs[sL];
+                    const Term t = diffusive_resolve(S, p);
+                    if (t.state != HIT_NONE) terminate<ARR>(a, bt, S, pid, p, t, acc);
+                }
             }
             const uint64_t M2 = __ballot(p.st == ST_DIFFUSIVE);
             stop = M2 == 0 || (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) ||
@@ -355,9 +373,13 @@ k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
     lds_flush(a, bt, acc);
 }
 
-// Diffusive phase of one round: the walks of the atoms queued by the ballistic phase.
+// Diffusive phase of one round: the walks of the atoms queued by the ballistic phase.  Lanes
+// of any segments walk together (the step needs only two per-lane numbers of the segment), so
+// a wave never falls back to one step at a time.  At most 128 VGPRs (four waves per SIMD):
+// the per-lane segment numbers and the per-segment test passes do not fit in 96 without
+// spilling.
 template <bool ARR>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5)))
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
 k_diffusive32(TransportArgs a, const SegDev<float>* __restrict__ segs)
 {
     extern __shared__ unsigned long long lds[];
@@ -371,6 +393,8 @@ k_diffusive32(TransportArgs a, const SegDev<float>* __restrict__ segs)
     p.e = p.ndiff = p.ncoll = 0;
     uint32_t pid = 0;
     int seg = 0;
+    float lam_th = 0.f;        // the lane's segment: thermal mean free path and Philox counter word
+    uint32_t cfgcat = 0;
     LaneAcc acc;
     Tickets T;
     for (;;) {
@@ -399,6 +423,8 @@ k_diffusive32(TransportArgs a, const SegDev<float>* __restrict__ segs)
                     acc.seg = sg;
                 }
                 seg = sg;
+                lam_th = segs[sg].lam_th;
+                cfgcat = segs[sg].cfgcat;
             }
         }
         const uint64_t D = __ballot(p.st == ST_DIFFUSIVE);
@@ -407,22 +433,14 @@ k_diffusive32(TransportArgs a, const SegDev<float>* __restrict__ segs)
             continue;
         }
         // Last walks of a drained wave: each is walked by the whole wave (up to 64 steps per
-        // pass) before the regular step below.
+        // pass) before the regular steps below.
         if (T.drained && __popcll(D) <= COOP_MAX) {
             for (uint64_t W = D; W != 0; W &= W - 1) {
                 const int L = __ffsll((unsigned long long)W) - 1;
                 coop_walk(segs[__builtin_amdgcn_readlane(seg, L)], a.k0, a.k1, a.cap, pid, p, L, lane);
             }
         }
-        const int s0 = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)D) - 1);
-        if (__ballot(p.st == ST_DIFFUSIVE && seg != s0) == 0) {
-            diffusive_loop<ARR>(a, bt, segs[s0], pid, p, acc, T.drained);
-        } else if (p.st == ST_DIFFUSIVE) {
-            // lanes of several segments: one step with per-lane constants
-            const SegDev<float>& s = segs[seg];
-            const Term t = step_diffusive_ball(s, a.k0, a.k1, pid, a.cap, p);
-            if (t.state != HIT_NONE) terminate<ARR>(a, bt, s, pid, p, t, acc);
-        }
+        diffusive_loop<ARR>(a, bt, segs, seg, lam_th, cfgcat, pid, p, acc, T.drained);
     }
     lds_flush(a, bt, acc);
 }
@@ -554,14 +572,15 @@ size_t transport32_lds(const Plan* P, bool arrivals, bool* lds_counters, bool* l
     return (*lds_counters ? cbytes : 0) + (*lds_tally ? tbytes : 0) + (*lds_arrivals ? abytes : 0);
 }
 
-int occupancy_transport32(const Plan* P, int threads, int* blocks_per_cu)
+int occupancy_transport32(const Plan* P, int threads, int* bpc_ballistic, int* bpc_diffusive)
 {
     bool lc, lt, la;
     const size_t smem = transport32_lds(P, false, &lc, &lt, &la);
     int b1 = 0, b2 = 0;
     SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_ballistic32<false>, threads, smem));
     SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_diffusive32<false>, threads, smem));
-    *blocks_per_cu = b1 < b2 ? b1 : b2;
+    *bpc_ballistic = b1;
+    *bpc_diffusive = b2;
     return SPX_OK;
 }
 
@@ -575,7 +594,7 @@ bool is_ballistic_kernel(const void* f)
 uint64_t rounds_of(uint64_t total) { return total == 0 ? 0 : (total + ROUND_MAX - 1) / ROUND_MAX; }
 
 int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st, const uint64_t* tfirst,
-                       uint64_t total, int blocks, int threads, int refill_min, int refill_ballistic,
+                       uint64_t total, int blocks, int blocks_diff, int threads, int refill_min, int refill_ballistic,
                        const hipEvent_t* events)
 {
     SPX_TRY(launch_zero(P, o, st));
@@ -631,9 +650,9 @@ int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st,
         SPX_HIP(hipGetLastError());
         if (events) SPX_HIP(hipEventRecord(events[3 * r + 1], st));
         if (a.arr_E)
-            hipLaunchKernelGGL(k_diffusive32<true>, dim3(blocks), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
+            hipLaunchKernelGGL(k_diffusive32<true>, dim3(blocks_diff), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
         else
-            hipLaunchKernelGGL(k_diffusive32<false>, dim3(blocks), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
+            hipLaunchKernelGGL(k_diffusive32<false>, dim3(blocks_diff), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
         SPX_HIP(hipGetLastError());
         if (events) SPX_HIP(hipEventRecord(events[3 * r + 2], st));
     }
