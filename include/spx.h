@@ -229,14 +229,15 @@ int spx_arrival_edges(double* h_energy_edges, double* h_cos_edges, float* h_ener
  * thresholds) by timing short runs on `stream`; synchronous; results are unaffected. */
 int spx_autotune(spx_plan* plan, void* stream);
 
-/* Current FP32-transport launch parameters, shared by its two persistent kernels (the
- * ballistic phase, launch to thermalisation, and the diffusive phase): blocks, threads per
- * block, the diffusive phase's refill threshold (a wave refills its dead lanes once at least
+/* Current FP32-transport launch parameters of its two persistent kernels (the ballistic
+ * phase, launch to thermalisation, and the diffusive phase): blocks (the ballistic grid; the
+ * diffusive kernel runs the smaller of it and its own resident limit), threads per block
+ * (both), the diffusive phase's refill threshold (a wave refills its dead lanes once at least
  * this many are dead) and the ballistic phase's.  Any pointer may be NULL. */
 int spx_get_launch(const spx_plan* plan, int32_t* blocks, int32_t* threads, int32_t* refill_min,
                    int32_t* refill_ballistic);
 /* Override them: threads a multiple of 64 in [64, 1024], thresholds in [1, 64]; blocks <= 0
- * (or above the resident limit) fills the device at the occupancy limit. */
+ * (or above the ballistic kernel's resident limit) fills the device at that limit. */
 int spx_set_launch(spx_plan* plan, int32_t blocks, int32_t threads, int32_t refill_min, int32_t refill_ballistic);
 
 /* Device time [ms] of the two phases of the last FP32 spx_run of this plan, summed over its

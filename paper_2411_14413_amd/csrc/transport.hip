@@ -18,6 +18,7 @@
 // one launch per segment.  It is the comparator for the batched path.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "spx_host.hpp"
@@ -286,17 +287,21 @@ __device__ __forceinline__ void diffusive_loop(const TransportArgs& a, const Blo
         bool stop = M == 0 || (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) ||
                     (drained && __popcll(M) <= COOP_MAX);
         if (H != 0 && (stop || H == M || __popcll(H) >= DEFER_MIN)) {
-            // the held steps, one segment at a time so that its geometry is read uniformly
-            for (uint64_t R = H; R != 0;) {
-                const int sL = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)R) - 1);
-                const bool mine = held && seg == sL;
-                R &= ~__ballot(mine);
-                if (mine) {
+            // the held steps: with the geometry read once for the wave when they share a
+            // segment (the common case), else each lane reading its own
+            const int sL = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)H) - 1);
+            if (__ballot(held && seg != sL) == 0) {
+                if (held) {
                     held = false;
                     const SegDev<float>& S = segs[sL];
                     const Term t = diffusive_resolve(S, p);
                     if (t.state != HIT_NONE) terminate<ARR>(a, bt, S, pid, p, t, acc);
                 }
+            } else if (held) {
+                held = false;
+                const SegDev<float>& S = segs[seg];
+                const Term t = diffusive_resolve(S, p);
+                if (t.state != HIT_NONE) terminate<ARR>(a, bt, S, pid, p, t, acc);
             }
             const uint64_t M2 = __ballot(p.st == ST_DIFFUSIVE);
             stop = M2 == 0 || (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) ||
@@ -375,12 +380,9 @@ k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
 
 // Diffusive phase of one round: the walks of the atoms queued by the ballistic phase.  Lanes
 // of any segments walk together (the step needs only two per-lane numbers of the segment), so
-// a wave never falls back to one step at a time.  At most 128 VGPRs (four waves per SIMD):
-// the per-lane segment numbers and the per-segment test passes do not fit in 96 without
-// spilling.
+// a wave never falls back to one step at a time.
 template <bool ARR>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
-k_diffusive32(TransportArgs a, const SegDev<float>* __restrict__ segs)
+__device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<float>* __restrict__ segs)
 {
     extern __shared__ unsigned long long lds[];
     BlockTally bt;
@@ -443,6 +445,19 @@ k_diffusive32(TransportArgs a, const SegDev<float>* __restrict__ segs)
         diffusive_loop<ARR>(a, bt, segs, seg, lam_th, cfgcat, pid, p, acc, T.drained);
     }
     lds_flush(a, bt, acc);
+}
+
+// At most 96 VGPRs without the arrival tallies (five waves per SIMD, as the ballistic phase);
+// with them, 128 (four waves), where five would spill.
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5)))
+k_diffusive32(TransportArgs a, const SegDev<float>* __restrict__ segs)
+{
+    diffusive_phase<false>(a, segs);
+}
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
+k_diffusive32_arr(TransportArgs a, const SegDev<float>* __restrict__ segs)
+{
+    diffusive_phase<true>(a, segs);
 }
 
 // Arrival outputs of the comparator (nullable as a group) with its FP64 bin edges.
@@ -578,7 +593,7 @@ int occupancy_transport32(const Plan* P, int threads, int* bpc_ballistic, int* b
     const size_t smem = transport32_lds(P, false, &lc, &lt, &la);
     int b1 = 0, b2 = 0;
     SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_ballistic32<false>, threads, smem));
-    SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_diffusive32<false>, threads, smem));
+    SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_diffusive32, threads, smem));
     *bpc_ballistic = b1;
     *bpc_diffusive = b2;
     return SPX_OK;
@@ -626,6 +641,12 @@ int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st,
     a.n_bins = (uint32_t)P->n_bins_total;
     bool lc, lt, la;
     const size_t smem = transport32_lds(P, o.arr_E != nullptr, &lc, &lt, &la);
+    int blocks_diff_arr = blocks_diff;
+    if (o.arr_E) {
+        int bpc_arr = 0;
+        SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc_arr, k_diffusive32_arr, threads, smem));
+        if (bpc_arr > 0) blocks_diff_arr = std::min(blocks_diff, bpc_arr * P->n_cu);
+    }
     a.lds_counters = lc ? 1 : 0;
     a.lds_tally = lt ? 1 : 0;
     a.lds_arrivals = la ? 1 : 0;
@@ -649,10 +670,13 @@ int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st,
             hipLaunchKernelGGL(k_ballistic32<false>, dim3(blocks), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
         SPX_HIP(hipGetLastError());
         if (events) SPX_HIP(hipEventRecord(events[3 * r + 1], st));
-        if (a.arr_E)
-            hipLaunchKernelGGL(k_diffusive32<true>, dim3(blocks_diff), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
-        else
-            hipLaunchKernelGGL(k_diffusive32<false>, dim3(blocks_diff), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
+        if (a.arr_E) {
+            // the instance with the tallies has its own resident limit (fewer waves per SIMD)
+            hipLaunchKernelGGL(k_diffusive32_arr, dim3(blocks_diff_arr), dim3(threads), smem, st, a,
+                               (const SegDev<float>*)P->d_seg32);
+        } else {
+            hipLaunchKernelGGL(k_diffusive32, dim3(blocks_diff), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
+        }
         SPX_HIP(hipGetLastError());
         if (events) SPX_HIP(hipEventRecord(events[3 * r + 2], st));
     }
