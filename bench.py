@@ -64,7 +64,7 @@ PEAK_ALU = 256 * 128 * 2.4e9
 # HBM bytes per launch of each kernel on the default workload from rocprofv3: FETCH_SIZE x 2.000
 # + WRITE_SIZE x 1.000 (KiB per dispatch; factors from a 1 GiB copy and fill).  Valid for the
 # kernels they were taken on; set to None when a kernel changes.
-TRAFFIC = {"k_diffusive32": None,
+TRAFFIC = {"k_diffusive32": 320_939 * 1024 * 2.000 + 36_269 * 1024 * 1.000,
            "k_ballistic32": 1_657 * 1024 * 2.000 + 712_945 * 1024 * 1.000}
 
 
