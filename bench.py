@@ -185,7 +185,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=25.0,
                     help="target of the CPU pilot-based sizing (the measured run usually takes about half)")
-    ap.add_argument("--launch", default="", help="blocks,threads,refill_min,refill_ballistic instead of autotuning")
+    ap.add_argument("--launch", default="", help="blocks,threads,refill_min,refill_ballistic[,defer_min] instead of autotuning")
     ap.add_argument("--arrivals", action="store_true",
                     help="also tally arrival energy and angle histograms and per-bin energy sums")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -219,8 +219,7 @@ def main():
     setup_s = time.perf_counter() - t
     t = time.perf_counter()
     if args.launch:
-        b_, t_, r_, m_ = (int(x) for x in args.launch.split(","))
-        launch = plan.set_launch(b_, t_, r_, m_)
+        launch = plan.set_launch(*(int(x) for x in args.launch.split(",")))
     else:
         launch = plan.launch if args.no_autotune else plan.autotune()
     tune_s = time.perf_counter() - t

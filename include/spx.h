@@ -225,20 +225,24 @@ int spx_run_ex(spx_plan* plan, uint64_t seed, const spx_outputs* out, void* stre
  * the double values rounded).  Any pointer may be NULL. */
 int spx_arrival_edges(double* h_energy_edges, double* h_cos_edges, float* h_energy_edges32, float* h_cos_edges32);
 
-/* Choose launch parameters of the FP32 transport (block size and the two refill
- * thresholds) by timing short runs on `stream`; synchronous; results are unaffected. */
+/* Choose launch parameters of the FP32 transport (block size, the two refill thresholds, then
+ * the deferral threshold) by timing short runs on `stream`; synchronous; results are
+ * unaffected. */
 int spx_autotune(spx_plan* plan, void* stream);
 
 /* Current FP32-transport launch parameters of its two persistent kernels (the ballistic
  * phase, launch to thermalisation, and the diffusive phase): blocks (the ballistic grid; the
  * diffusive kernel runs the smaller of it and its own resident limit), threads per block
  * (both), the diffusive phase's refill threshold (a wave refills its dead lanes once at least
- * this many are dead) and the ballistic phase's.  Any pointer may be NULL. */
+ * this many are dead), the ballistic phase's, and the diffusive phase's deferral threshold (a
+ * wave tests the steps that left their clearance balls once at least this many lanes hold
+ * one; default 8).  Any pointer may be NULL. */
 int spx_get_launch(const spx_plan* plan, int32_t* blocks, int32_t* threads, int32_t* refill_min,
-                   int32_t* refill_ballistic);
+                   int32_t* refill_ballistic, int32_t* defer_min);
 /* Override them: threads a multiple of 64 in [64, 1024], thresholds in [1, 64]; blocks <= 0
  * (or above the ballistic kernel's resident limit) fills the device at that limit. */
-int spx_set_launch(spx_plan* plan, int32_t blocks, int32_t threads, int32_t refill_min, int32_t refill_ballistic);
+int spx_set_launch(spx_plan* plan, int32_t blocks, int32_t threads, int32_t refill_min, int32_t refill_ballistic,
+                   int32_t defer_min);
 
 /* Device time [ms] of the two phases of the last FP32 spx_run of this plan, summed over its
  * rounds (HIP events recorded between the kernels; waits for that run to finish).

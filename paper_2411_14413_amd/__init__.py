@@ -197,14 +197,15 @@ class Plan:
 
     @property
     def launch(self):
-        b, t, r, m = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        check(lib().spx_get_launch(self._h, ctypes.byref(b), ctypes.byref(t), ctypes.byref(r), ctypes.byref(m)),
-              "spx_get_launch")
-        return dict(blocks=b.value, threads=t.value, refill_min=r.value, refill_ballistic=m.value)
+        b, t, r, m, d = (ctypes.c_int32() for _ in range(5))
+        check(lib().spx_get_launch(self._h, ctypes.byref(b), ctypes.byref(t), ctypes.byref(r), ctypes.byref(m),
+                                   ctypes.byref(d)), "spx_get_launch")
+        return dict(blocks=b.value, threads=t.value, refill_min=r.value, refill_ballistic=m.value, defer_min=d.value)
 
-    def set_launch(self, blocks: int = 0, threads: int = 256, refill_min: int = 8, refill_ballistic: int = 8):
-        check(lib().spx_set_launch(self._h, int(blocks), int(threads), int(refill_min), int(refill_ballistic)),
-              "spx_set_launch")
+    def set_launch(self, blocks: int = 0, threads: int = 256, refill_min: int = 8, refill_ballistic: int = 8,
+                   defer_min: int = 8):
+        check(lib().spx_set_launch(self._h, int(blocks), int(threads), int(refill_min), int(refill_ballistic),
+                                   int(defer_min)), "spx_set_launch")
         return self.launch
 
     def phase_times(self):

@@ -93,8 +93,8 @@ SIGNATURES = {
                                          ctypes.POINTER(ctypes.c_float)]),
     "spx_autotune": (ctypes.c_int, [_vp, _vp]),
     "spx_get_launch": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
-                                      ctypes.POINTER(_i32)]),
-    "spx_set_launch": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32]),
+                                      ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "spx_set_launch": (ctypes.c_int, [_vp, _i32, _i32, _i32, _i32, _i32]),
     "spx_phase_times": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     "spx_get_table": (ctypes.c_int, [_vp, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl)]),
     "spx_segment_info": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_dbl)]),

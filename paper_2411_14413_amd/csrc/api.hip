@@ -709,6 +709,7 @@ static int run(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st)
     key.threads = P->threads;
     key.refill = P->refill_min;
     key.refill_b = P->refill_ballistic;
+    key.defer = P->defer_min;
     if (!P->graph_exec || !(key == P->graph_key)) {
         if (P->graph_exec) {
             SPX_HIP(hipGraphExecDestroy(P->graph_exec));
@@ -720,7 +721,8 @@ static int run(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st)
         }
         SPX_HIP(hipStreamBeginCapture(P->work_stream, hipStreamCaptureModeThreadLocal));
         const int rc = launch_transport32(P, seed, o, P->work_stream, P->d_tfirst, P->n_tickets, P->blocks,
-                                          P->blocks_diff, P->threads, P->refill_min, P->refill_ballistic, nullptr);
+                                          P->blocks_diff, P->threads, P->refill_min, P->refill_ballistic,
+                                          P->defer_min, nullptr);
         hipGraph_t g = nullptr;
         const hipError_t ec = hipStreamEndCapture(P->work_stream, &g);
         if (rc != SPX_OK) {
@@ -773,8 +775,26 @@ static int autotune(Plan* P, hipStream_t st)
     if (rc == SPX_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = SPX_EDEVICE;
     if (rc == SPX_OK && hipMemcpyAsync(d_tf, tf.data(), sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess)
         rc = SPX_EDEVICE;
+    // best of two timed runs of one launch shape on the sample
+    auto time_shape = [&](int blocks, int blocks_d, int t, int rmin, int rbal, int defer) -> float {
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 2 && rc == SPX_OK; ++rep) {
+            if (hipEventRecord(e0, st) != hipSuccess) rc = SPX_EDEVICE;
+            Outputs to;
+            to.counts = d_counts;
+            to.counters = d_ctr;
+            if (rc == SPX_OK)
+                rc = launch_transport32(P, 0x5eed, to, st, d_tf, tf[n], blocks, blocks_d, t, rmin, rbal, defer, nullptr);
+            if (rc == SPX_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                rc = SPX_EDEVICE;
+            float ms = 0.f;
+            if (rc == SPX_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms_min = std::min(ms_min, ms);
+        }
+        return ms_min;
+    };
     float best = 1e30f;
     int bb = P->blocks, bd = P->blocks_diff, bt = P->threads, br = P->refill_min, bm = P->refill_ballistic;
+    int bdef = DEFER_MIN;
     const int thread_opts[] = {256, 512, 1024};
     const int mode_opts[][2] = {{4, 4}, {4, 16}, {8, 8}};   // (refill_min, refill_ballistic)
     for (int t : thread_opts) {
@@ -783,27 +803,25 @@ static int autotune(Plan* P, hipStream_t st)
         if (occupancy_transport32(P, t, &bpc, &bpc_d) != SPX_OK || bpc < 1 || bpc_d < 1) continue;
         for (const auto& ro : mode_opts) {
             const int blocks = bpc * P->n_cu, blocks_d = std::min(blocks, bpc_d * P->n_cu);
-            float ms_min = 1e30f;
-            for (int rep = 0; rep < 2 && rc == SPX_OK; ++rep) {
-                if (hipEventRecord(e0, st) != hipSuccess) rc = SPX_EDEVICE;
-                Outputs to;
-                to.counts = d_counts;
-                to.counters = d_ctr;
-                if (rc == SPX_OK)
-                    rc = launch_transport32(P, 0x5eed, to, st, d_tf, tf[n], blocks, blocks_d, t, ro[0], ro[1], nullptr);
-                if (rc == SPX_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
-                    rc = SPX_EDEVICE;
-                float ms = 0.f;
-                if (rc == SPX_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms_min = std::min(ms_min, ms);
-            }
-            if (rc == SPX_OK && ms_min < best) {
-                best = ms_min;
+            const float ms = time_shape(blocks, blocks_d, t, ro[0], ro[1], DEFER_MIN);
+            if (rc == SPX_OK && ms < best) {
+                best = ms;
                 bb = blocks;
                 bd = blocks_d;
                 bt = t;
                 br = ro[0];
                 bm = ro[1];
             }
+        }
+    }
+    // then the deferral threshold for that shape: more held steps per test pass pays off where
+    // steps leave their clearance balls often (near surfaces, absorbing objects)
+    for (int defer : {2 * DEFER_MIN}) {
+        if (rc != SPX_OK) break;
+        const float ms = time_shape(bb, bd, bt, br, bm, defer);
+        if (rc == SPX_OK && ms < best) {
+            best = ms;
+            bdef = defer;
         }
     }
     if (e0) (void)hipEventDestroy(e0);
@@ -817,6 +835,7 @@ static int autotune(Plan* P, hipStream_t st)
     }
     P->blocks = bb;
     P->blocks_diff = bd;
+    P->defer_min = bdef;
     P->threads = bt;
     P->refill_min = br;
     P->refill_ballistic = bm;
@@ -938,22 +957,25 @@ int spx_autotune(spx_plan* P, void* stream)
 }
 
 int spx_get_launch(const spx_plan* P, int32_t* blocks, int32_t* threads, int32_t* refill_min,
-                   int32_t* refill_ballistic)
+                   int32_t* refill_ballistic, int32_t* defer_min)
 {
     if (!P) return fail("null plan");
     if (blocks) *blocks = P->blocks;
     if (threads) *threads = P->threads;
     if (refill_min) *refill_min = P->refill_min;
     if (refill_ballistic) *refill_ballistic = P->refill_ballistic;
+    if (defer_min) *defer_min = P->defer_min;
     return SPX_OK;
 }
 
-int spx_set_launch(spx_plan* P, int32_t blocks, int32_t threads, int32_t refill_min, int32_t refill_ballistic)
+int spx_set_launch(spx_plan* P, int32_t blocks, int32_t threads, int32_t refill_min, int32_t refill_ballistic,
+                   int32_t defer_min)
 {
     if (!P) return fail("null plan");
     if (threads < 64 || threads > 1024 || (threads & 63)) return fail("threads must be a multiple of 64 in [64, 1024]");
     if (refill_min < 1 || refill_min > 64) return fail("refill_min must be in [1, 64]");
     if (refill_ballistic < 1 || refill_ballistic > 64) return fail("refill_ballistic must be in [1, 64]");
+    if (defer_min < 1 || defer_min > 64) return fail("defer_min must be in [1, 64]");
     int bpc = 0, bpc_d = 0;
     SPX_TRY(occupancy_transport32(P, threads, &bpc, &bpc_d));
     if (bpc < 1 || bpc_d < 1) return fail("transport kernels do not fit with this block size");
@@ -965,6 +987,7 @@ int spx_set_launch(spx_plan* P, int32_t blocks, int32_t threads, int32_t refill_
     P->threads = threads;
     P->refill_min = refill_min;
     P->refill_ballistic = refill_ballistic;
+    P->defer_min = defer_min;
     return SPX_OK;
 }
 

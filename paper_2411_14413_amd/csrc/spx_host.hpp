@@ -86,6 +86,7 @@ struct TransportArgs {
     int32_t n_seg;
     int32_t refill_min;         // diffusive phase: refill a wave's dead lanes once at least this many
     int32_t refill_ballistic;   // ballistic phase: the same threshold
+    int32_t defer_min;          // diffusive phase: held steps that trigger a wave's surface tests
     uint32_t n_bins;            // tally bins of the plan
     int32_t lds_counters;       // per-segment counters privatised in LDS
     int32_t lds_tally;          // whole tally privatised in LDS (u32 per bin)
@@ -110,7 +111,7 @@ constexpr size_t LDS_COUNTERS_MAX = 16384;   // bytes: up to 292 segments
 constexpr int RT_MAX_NODES = 256;             // nodes of a measured racetrack profile
 constexpr int OBJ_MAX_SEG = 32;               // absorbing objects of one (config, cathode) run
 constexpr uint64_t TICKET_CHUNK = 64;        // tickets a wave claims per global atomic
-constexpr int DEFER_MIN = 8;                  // held diffusive steps that trigger a wave's surface tests
+constexpr int DEFER_MIN = 8;                  // default: held diffusive steps that trigger a wave's surface tests
 constexpr int COOP_MAX = 8;                   // drained waves with at most this many live lanes walk cooperatively
 constexpr size_t LDS_TALLY_MAX = 49152;      // bytes: up to 12288 bins
 constexpr size_t LDS_ARRIVALS_MAX = 4096;     // bytes: arrival histograms of up to 6 segments
@@ -124,12 +125,12 @@ struct GraphKey {
     void* arr_E = nullptr;
     void* arr_A = nullptr;
     void* esum = nullptr;
-    int blocks = 0, threads = 0, refill = 0, refill_b = 0;
+    int blocks = 0, threads = 0, refill = 0, refill_b = 0, defer = 0;
     bool operator==(const GraphKey& o) const
     {
         return seed == o.seed && counts == o.counts && counters == o.counters && profiles == o.profiles &&
-               records == o.records && arr_E == o.arr_E && arr_A == o.arr_A && esum == o.esum && blocks == o.blocks && threads == o.threads && refill == o.refill &&
-               refill_b == o.refill_b;
+               records == o.records && arr_E == o.arr_E && arr_A == o.arr_A && esum == o.esum && blocks == o.blocks &&
+               threads == o.threads && refill == o.refill && refill_b == o.refill_b && defer == o.defer;
     }
 };
 
@@ -168,7 +169,7 @@ struct spx_plan {
     double* d_seg_norm = nullptr;           // [n_seg]
     uint64_t n_tickets = 0;
 
-    int blocks = 0, threads = 256, refill_min = 8, refill_ballistic = 8;
+    int blocks = 0, threads = 256, refill_min = 8, refill_ballistic = 8, defer_min = spx::DEFER_MIN;
     int blocks_diff = 0;                    // grid of the diffusive kernel: blocks, capped at its resident limit
     int max_blocks_per_cu = 0, n_cu = 0;
 
@@ -184,7 +185,7 @@ int build_tables(Plan* P);
 // its ballistic phase and after its diffusive phase.
 int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st, const uint64_t* tfirst,
                        uint64_t total, int blocks, int blocks_diff, int threads, int refill_min, int refill_ballistic,
-                       const hipEvent_t* events);
+                       int defer_min, const hipEvent_t* events);
 uint64_t rounds_of(uint64_t total);
 bool is_ballistic_kernel(const void* f);
 int launch_transport64(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st);

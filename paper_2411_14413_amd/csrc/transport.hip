@@ -257,7 +257,7 @@ __device__ __forceinline__ void ballistic_loop(const TransportArgs& a, const Blo
 }
 
 // Diffusive steps of the lanes in segment S with deferred surface tests: a lane whose
-// step leaves its clearance ball holds the step and idles until at least DEFER_MIN lanes
+// step leaves its clearance ball holds the step and idles until at least a.defer_min lanes
 // hold one (or every diffusive lane does, or the loop is about to end); then the held
 // steps are tested together, so the long test runs in few iterations.  No step is held
 // when the loop returns.
@@ -286,7 +286,7 @@ __device__ __forceinline__ void diffusive_loop(const TransportArgs& a, const Blo
         const uint64_t M = __ballot(p.st == ST_DIFFUSIVE);
         bool stop = M == 0 || (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) ||
                     (drained && __popcll(M) <= COOP_MAX);
-        if (H != 0 && (stop || H == M || __popcll(H) >= DEFER_MIN)) {
+        if (H != 0 && (stop || H == M || __popcll(H) >= a.defer_min)) {
             // the held steps: with the geometry read once for the wave when they share a
             // segment (the common case), else each lane reading its own
             const int sL = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)H) - 1);
@@ -610,7 +610,7 @@ uint64_t rounds_of(uint64_t total) { return total == 0 ? 0 : (total + ROUND_MAX 
 
 int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st, const uint64_t* tfirst,
                        uint64_t total, int blocks, int blocks_diff, int threads, int refill_min, int refill_ballistic,
-                       const hipEvent_t* events)
+                       int defer_min, const hipEvent_t* events)
 {
     SPX_TRY(launch_zero(P, o, st));
     TransportArgs a;
@@ -638,6 +638,7 @@ int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st,
     a.n_seg = P->n_seg;
     a.refill_min = refill_min;
     a.refill_ballistic = refill_ballistic;
+    a.defer_min = defer_min;
     a.n_bins = (uint32_t)P->n_bins_total;
     bool lc, lt, la;
     const size_t smem = transport32_lds(P, o.arr_E != nullptr, &lc, &lt, &la);

@@ -94,8 +94,9 @@ def test_absorber_determinism_across_launch_shapes():
     say("absorbers: determinism across launch shapes")
     plan = spx.Plan(cfgs, PARAMS)
     results = []
-    for blocks, threads, refill, bmin in ((0, 256, 4, 4), (0, 1024, 8, 8), (7, 64, 64, 64), (300, 512, 4, 16)):
-        plan.set_launch(blocks, threads, refill, bmin)
+    for blocks, threads, refill, bmin, defer in ((0, 256, 4, 4, 8), (0, 1024, 8, 8, 16), (7, 64, 64, 64, 2),
+                                                 (300, 512, 4, 16, 32)):
+        plan.set_launch(blocks, threads, refill, bmin, defer)
         out = plan.run(seed=12, records=True)
         torch.cuda.synchronize()
         results.append((out["counts"].cpu().numpy(), out["counters"].cpu().numpy(), out["records"].cpu().numpy()))

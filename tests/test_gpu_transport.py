@@ -134,9 +134,9 @@ def test_determinism_across_launch_shapes():
     say("determinism: launch shapes")
     plan = spx.Plan(cfgs, PARAMS)
     results = []
-    for blocks, threads, refill, bmin in ((0, 256, 1, 1), (0, 1024, 24, 32), (7, 64, 64, 64), (300, 512, 8, 3),
-                                          (0, 512, 1, 64)):
-        plan.set_launch(blocks, threads, refill, bmin)
+    for blocks, threads, refill, bmin, defer in ((0, 256, 1, 1, 8), (0, 1024, 24, 32, 16), (7, 64, 64, 64, 1),
+                                                 (300, 512, 8, 3, 64), (0, 512, 1, 64, 5)):
+        plan.set_launch(blocks, threads, refill, bmin, defer)
         out = plan.run(seed=11, records=True)
         torch.cuda.synchronize()
         results.append((out["counts"].cpu().numpy(), out["counters"].cpu().numpy(), out["records"].cpu().numpy()))
