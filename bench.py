@@ -63,7 +63,8 @@ OPS = dict(
 PEAK_ALU = 256 * 128 * 2.4e9
 # HBM bytes per launch of each kernel on the default workload from rocprofv3: FETCH_SIZE x 2.000
 # + WRITE_SIZE x 1.000 (KiB per dispatch; factors from a 1 GiB copy and fill).  Valid for the
-# kernels they were taken on; set to None when a kernel changes.
+# kernels and the workload they were taken on (reported for that workload only); set to None
+# when a kernel changes.
 TRAFFIC = {"k_diffusive32": 320_939 * 1024 * 2.000 + 36_269 * 1024 * 1.000,
            "k_ballistic32": 1_657 * 1024 * 2.000 + 712_945 * 1024 * 1.000}
 
@@ -259,7 +260,8 @@ def main():
     ops, ms_k = kern[dominant]
     achieved = ops / (ms_k * 1e-3)
     roofline = dict(bound="alu", kernel=dominant, achieved=achieved / 1e12, peak=PEAK_ALU / 1e12,
-                    unit="TOP/s", frac=achieved / PEAK_ALU, traffic=TRAFFIC.get(dominant),
+                    unit="TOP/s", frac=achieved / PEAK_ALU,
+                    traffic=TRAFFIC.get(dominant) if args.workload == "legs" and not args.arrivals else None,
                     ops_per_launch=ops, launch_ms=ms_k,
                     phases={k: dict(ops=o, ms=t, achieved=o / (t * 1e-3) / 1e12 if t > 0 else None,
                                     frac=o / (t * 1e-3) / PEAK_ALU if t > 0 else None) for k, (o, t) in kern.items()},
