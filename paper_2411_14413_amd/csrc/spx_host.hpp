@@ -87,6 +87,7 @@ struct TransportArgs {
     int32_t refill_min;         // diffusive phase: refill a wave's dead lanes once at least this many
     int32_t refill_ballistic;   // ballistic phase: the same threshold
     int32_t defer_min;          // diffusive phase: held steps that trigger a wave's surface tests
+    uint32_t chunk_ballistic;   // ballistic phase: tickets a wave claims per atomic
     uint32_t n_bins;            // tally bins of the plan
     int32_t lds_counters;       // per-segment counters privatised in LDS
     int32_t lds_tally;          // whole tally privatised in LDS (u32 per bin)
@@ -110,7 +111,11 @@ constexpr uint64_t QUEUE_SLACK_WAVES = 8192;  // waves that may leave slots unus
 constexpr size_t LDS_COUNTERS_MAX = 16384;   // bytes: up to 292 segments
 constexpr int RT_MAX_NODES = 256;             // nodes of a measured racetrack profile
 constexpr int OBJ_MAX_SEG = 32;               // absorbing objects of one (config, cathode) run
-constexpr uint64_t TICKET_CHUNK = 64;        // tickets a wave claims per global atomic
+constexpr uint64_t TICKET_CHUNK = 64;        // queued atoms a diffusive wave claims per global atomic
+// launch tickets a ballistic wave claims per global atomic, at most: ballistic histories are
+// short, so their waves come back for tickets often and small chunks queue them on the one
+// counter; the chunk of a round is also kept small enough for every wave to take several
+constexpr uint64_t TICKET_CHUNK_BALLISTIC_MAX = 512;
 constexpr int DEFER_MIN = 8;                  // default: held diffusive steps that trigger a wave's surface tests
 constexpr int COOP_MAX = 8;                   // drained waves with at most this many live lanes walk cooperatively
 constexpr size_t LDS_TALLY_MAX = 49152;      // bytes: up to 12288 bins

@@ -117,8 +117,8 @@ __device__ __forceinline__ void terminate(const TransportArgs& a, const BlockTal
     p.st = ST_DEAD;
 }
 
-// Wave-private run of tickets [tk, tk_end), claimed TICKET_CHUNK at a time from a global
-// counter with one atomic, so that refills rarely touch the counter.
+// Wave-private run of tickets [tk, tk_end), claimed CHUNK at a time from a global counter with
+// one atomic, so that refills rarely touch the counter.
 struct Tickets {
     uint64_t tk = 0, tk_end = 0;
     bool drained = false;     // wave-uniform: the ticket space is exhausted
@@ -126,19 +126,19 @@ struct Tickets {
 
 // Tickets for the dead lanes `dead` of the wave: consecutive tickets of the wave's run in lane
 // order.  Returns this lane's ticket, or ~0 when it gets none.
-__device__ __forceinline__ uint64_t claim(Tickets& T, uint64_t* counter, uint64_t total, uint64_t dead, int lane,
-                                          uint64_t lt_mask)
+__device__ __forceinline__ uint64_t claim(Tickets& T, uint64_t* counter, uint64_t chunk, uint64_t total, uint64_t dead,
+                                          int lane, uint64_t lt_mask)
 {
     if (T.tk == T.tk_end) {
         unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd((unsigned long long*)counter, (unsigned long long)TICKET_CHUNK);
+        if (lane == 0) base = atomicAdd((unsigned long long*)counter, (unsigned long long)chunk);
         base = __shfl(base, 0);
         if (base >= total) {
             T.drained = true;
             return ~0ull;
         }
         T.tk = base;
-        T.tk_end = (base + TICKET_CHUNK < total) ? base + TICKET_CHUNK : total;
+        T.tk_end = (base + chunk < total) ? base + chunk : total;
     }
     const uint64_t n_dead = (uint64_t)__popcll(dead);
     const uint64_t avail = T.tk_end - T.tk;
@@ -337,7 +337,7 @@ k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
         const uint64_t dead = __ballot(p.st == ST_DEAD);
         const int n_dead = __popcll(dead);
         if (!T.drained && n_dead > 0 && (n_dead >= a.refill_ballistic || n_dead == 64)) {
-            const uint64_t my = claim(T, &a.qstate[0], a.total, dead, lane, lt_mask);
+            const uint64_t my = claim(T, &a.qstate[0], a.chunk_ballistic, a.total, dead, lane, lt_mask);
             if (my != ~0ull) {
                 const uint64_t g = a.tbase + my;
                 int lo = 0, hi = a.n_seg;
@@ -403,7 +403,7 @@ __device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<f
         const uint64_t dead = __ballot(p.st == ST_DEAD);
         const int n_dead = __popcll(dead);
         if (!T.drained && n_dead > 0 && (n_dead >= a.refill_min || n_dead == 64)) {
-            const uint64_t my = claim(T, &a.qstate[2], total, dead, lane, lt_mask);
+            const uint64_t my = claim(T, &a.qstate[2], TICKET_CHUNK, total, dead, lane, lt_mask);
             const uint32_t qpid = my != ~0ull ? a.queue[my].pid : 0xFFFFFFFFu;
             if (qpid != 0xFFFFFFFFu) {                 // empty slots (left unused by a wave) are skipped
                 const ThermRec r = a.queue[my];
@@ -662,6 +662,11 @@ int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st,
     for (uint64_t r = 0; r < n_rounds; ++r) {
         a.tbase = r * per_round;
         a.total = (a.tbase + per_round < total) ? per_round : total - a.tbase;
+        // the largest power-of-two chunk in [TICKET_CHUNK, TICKET_CHUNK_BALLISTIC_MAX] that
+        // still gives every wave about four chunks of the round
+        uint64_t cb = TICKET_CHUNK;
+        while (2 * cb <= TICKET_CHUNK_BALLISTIC_MAX && 2 * cb * 4 * waves <= a.total) cb *= 2;
+        a.chunk_ballistic = (uint32_t)cb;
         if (events) SPX_HIP(hipEventRecord(events[3 * r], st));
         hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(64), 0, st, P->d_qstate);
         SPX_HIP(hipGetLastError());
