@@ -66,7 +66,7 @@ PEAK_ALU = 256 * 128 * 2.4e9
 # kernels and the workload they were taken on (reported for that workload only); set to None
 # when a kernel changes.
 TRAFFIC = {"k_diffusive32": 320_939 * 1024 * 2.000 + 36_269 * 1024 * 1.000,
-           "k_ballistic32": 1_657 * 1024 * 2.000 + 712_945 * 1024 * 1.000}
+           "k_ballistic32": None}
 
 
 def algorithmic_ops(counters):
