@@ -355,6 +355,7 @@ template <typename R> static SegDev<R> to_device(const Plan* P, const SegHost& s
     d.vg = (R)s.vg;
     d.E_th = (R)s.E_th;
     d.lam_th = (R)s.lam_th;
+    d.lam_l2 = (R)(s.lam_th * 0.69314718055994530942);
     d.z_mid = (R)s.z_mid;
     d.shape = s.shape;
     d.nu = s.nu;

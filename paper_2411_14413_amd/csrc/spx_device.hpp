@@ -174,6 +174,7 @@ template <typename R> struct SegDev {
     R n_pia2;                             // n pi a^2: n sigma = n_pia2 * beta_max^2
     R vth, inv_vg, vg;                    // Maxwellian component sd; mean-speed scale
     R E_th, lam_th;
+    R lam_l2;                             // lam_th ln 2: a diffusive step is -lam_l2 log2(RN)
     R z_mid;                              // chamber-frame origin along z (world z = z' + z_mid)
     int32_t shape, nu, nv, gas_motion;
     int32_t vacuum, rt_n;
@@ -539,19 +540,21 @@ __device__ __forceinline__ void collide(const SegDev<R>& s, const TabDev<R>& tb,
 }
 
 // Isotropic direction and exponential step (mean lam_th, the segment's thermal mean free path)
-// of a thermalised atom from its three 21-bit codes (length, direction cosine, azimuth).
+// of a thermalised atom from its three 21-bit codes (length, direction cosine, azimuth).  The
+// step -lam_th ln(RN) is formed as -(lam_th ln 2) log2(RN) with lam_l2 = lam_th ln 2, and
+// sin^2 = 1 - mu^2 with one fused multiply-add (exact product, one rounding).
 template <typename R>
-__device__ __forceinline__ R diffusive_draw(R lam_th, const uint32_t* k, R* d)
+__device__ __forceinline__ R diffusive_draw(R lam_l2, const uint32_t* k, R* d)
 {
     const R u0 = u21<R>(k[0]), u1 = u21<R>(k[1]), u2 = u21<R>(k[2]);
     const R mu = (R)2 * u1 - (R)1;
-    const R st = m_sqrt(((R)1 - mu) * ((R)1 + mu));
+    const R st = m_sqrt(fma(-mu, mu, (R)1));
     R sp, cp;
     m_sincos2pi(u2, &sp, &cp);
     d[0] = st * cp;
     d[1] = st * sp;
     d[2] = mu;
-    return -lam_th * m_log(u0);
+    return -lam_l2 * m_log2(u0);
 }
 
 // Compensated (Kahan) accumulation: the position is s - c with c the rounding lost so far,
@@ -605,7 +608,7 @@ __device__ __forceinline__ Term step_mode(const SegDev<R>& s, const TabDev<R>& t
     } else {
         uint32_t k[3];
         diffusive_codes(diffusive_block(pid, e, s.cfgcat, k0, k1), (e & 1u) != 0, k);
-        ell = diffusive_draw(s.lam_th, k, p.d);   // diffusive only after a gas collision: never in vacuum
+        ell = diffusive_draw(s.lam_l2, k, p.d);   // diffusive only after a gas collision: never in vacuum
     }
     R t, qu = (R)0, qv = (R)0;
     const HitF h = hit_test(s, p.x, p.d, ell, t, qu, qv, e == 1u);
@@ -695,13 +698,13 @@ constexpr float CLEAR_MARGIN = 0.02f;
 // One diffusive sub-step from block w (the odd or the even half) for a lane where `active`;
 // straight-line code ending in selects, so that inactive lanes keep their state and no
 // branch splits the wave.
-__device__ __forceinline__ void diffusive_substep(float lam_th, uint4 w, bool odd, bool active, Particle<float>& p,
+__device__ __forceinline__ void diffusive_substep(float lam_l2, uint4 w, bool odd, bool active, Particle<float>& p,
                                                   bool& held)
 {
     uint32_t k[3];
     diffusive_codes(w, odd, k);
     float dir[3], v[3];
-    const float ell = diffusive_draw(lam_th, k, dir);   // diffusive only after a gas collision
+    const float ell = diffusive_draw(lam_l2, k, dir);   // diffusive only after a gas collision
     step_vector(ell, dir, v);
     float y[3], t[3];
     kahan_try(p.x, p.xc, v, y, t);
@@ -721,15 +724,15 @@ __device__ __forceinline__ void diffusive_substep(float lam_th, uint4 w, bool od
     held = held || hold;
 }
 
-__device__ __forceinline__ Term diffusive_advance(float lam_th, uint32_t cfgcat, uint32_t k0, uint32_t k1,
+__device__ __forceinline__ Term diffusive_advance(float lam_l2, uint32_t cfgcat, uint32_t k0, uint32_t k1,
                                                   uint32_t pid, uint32_t cap, Particle<float>& p, bool& held)
 {
     if (p.e >= cap) return Term{HIT_ESCAPED, -1, 0.f};
     const uint4 w = diffusive_block(pid, p.e + 1, cfgcat, k0, k1);
     // the even step of the block (if the next event is even), then its odd step unless the
     // even one is held or the cap is reached (a capped history escapes at its next step)
-    diffusive_substep(lam_th, w, false, ((p.e + 1) & 1u) == 0, p, held);
-    diffusive_substep(lam_th, w, true, !held && p.e < cap, p, held);
+    diffusive_substep(lam_l2, w, false, ((p.e + 1) & 1u) == 0, p, held);
+    diffusive_substep(lam_l2, w, true, !held && p.e < cap, p, held);
     return Term{HIT_NONE, -1, 0.f};
 }
 
@@ -782,7 +785,7 @@ __device__ __forceinline__ void coop_walk(const SegDev<float>& s, uint32_t k0, u
     uint32_t kc[3];
     diffusive_codes(diffusive_block(pidL, ej, s.cfgcat, k0, k1), (ej & 1u) != 0, kc);
     float dir[3], v[3];
-    const float ell = diffusive_draw(s.lam_th, kc, dir);
+    const float ell = diffusive_draw(s.lam_l2, kc, dir);
     step_vector(ell, dir, v);
     // steps that may be taken at all: within the event cap (the ball test rejects the rest)
     const uint64_t allowed = __ballot(ej <= cap);

@@ -263,7 +263,7 @@ __device__ __forceinline__ void ballistic_loop(const TransportArgs& a, const Blo
 // when the loop returns.
 template <bool ARR>
 __device__ __forceinline__ void diffusive_loop(const TransportArgs& a, const BlockTally& bt,
-                                               const SegDev<float>* __restrict__ segs, int seg, float lam_th,
+                                               const SegDev<float>* __restrict__ segs, int seg, float lam_l2,
                                                uint32_t cfgcat, uint32_t pid, Particle<float>& p, LaneAcc& acc,
                                                bool drained)
 {
@@ -271,7 +271,7 @@ __device__ __forceinline__ void diffusive_loop(const TransportArgs& a, const Blo
     for (;;) {
         bool capped = false;
         if (p.st == ST_DIFFUSIVE && !held)
-            capped = diffusive_advance(lam_th, cfgcat, a.k0, a.k1, pid, a.cap, p, held).state != HIT_NONE;
+            capped = diffusive_advance(lam_l2, cfgcat, a.k0, a.k1, pid, a.cap, p, held).state != HIT_NONE;
         // histories at the event cap escape (rare): ended one segment at a time
         for (uint64_t R = __ballot(capped); R != 0;) {
             const int sL = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)R) - 1);
@@ -395,7 +395,7 @@ __device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<f
     p.e = p.ndiff = p.ncoll = 0;
     uint32_t pid = 0;
     int seg = 0;
-    float lam_th = 0.f;        // the lane's segment: thermal mean free path and Philox counter word
+    float lam_l2 = 0.f;        // the lane's segment: thermal mean free path (times ln 2), Philox word
     uint32_t cfgcat = 0;
     LaneAcc acc;
     Tickets T;
@@ -425,7 +425,7 @@ __device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<f
                     acc.seg = sg;
                 }
                 seg = sg;
-                lam_th = segs[sg].lam_th;
+                lam_l2 = segs[sg].lam_l2;
                 cfgcat = segs[sg].cfgcat;
             }
         }
@@ -442,7 +442,7 @@ __device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<f
                 coop_walk(segs[__builtin_amdgcn_readlane(seg, L)], a.k0, a.k1, a.cap, pid, p, L, lane);
             }
         }
-        diffusive_loop<ARR>(a, bt, segs, seg, lam_th, cfgcat, pid, p, acc, T.drained);
+        diffusive_loop<ARR>(a, bt, segs, seg, lam_l2, cfgcat, pid, p, acc, T.drained);
     }
     lds_flush(a, bt, acc);
 }
