@@ -817,13 +817,11 @@ static int autotune(Plan* P, hipStream_t st)
     }
     // then the deferral threshold for that shape: more held steps per test pass pays off where
     // steps leave their clearance balls often (near surfaces, absorbing objects)
-    for (int defer : {2 * DEFER_MIN}) {
-        if (rc != SPX_OK) break;
+    for (int defer = 2 * DEFER_MIN; defer <= 4 * DEFER_MIN && rc == SPX_OK; defer *= 2) {
         const float ms = time_shape(bb, bd, bt, br, bm, defer);
-        if (rc == SPX_OK && ms < best) {
-            best = ms;
-            bdef = defer;
-        }
+        if (rc != SPX_OK || !(ms < best)) break;     // doubling again only while it helps
+        best = ms;
+        bdef = defer;
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
