@@ -269,9 +269,13 @@ __device__ __forceinline__ void diffusive_loop(const TransportArgs& a, const Blo
 {
     bool held = false;
     for (;;) {
+        // several advances (two steps each) between the wave's checks below: a lane that holds
+        // a step, or reaches the cap, sits out the rest of them
         bool capped = false;
-        if (p.st == ST_DIFFUSIVE && !held)
-            capped = diffusive_advance(lam_l2, cfgcat, a.k0, a.k1, pid, a.cap, p, held).state != HIT_NONE;
+#pragma unroll
+        for (int rep = 0; rep < ADVANCES_PER_CHECK; ++rep)
+            if (p.st == ST_DIFFUSIVE && !held && !capped)
+                capped = diffusive_advance(lam_l2, cfgcat, a.k0, a.k1, pid, a.cap, p, held).state != HIT_NONE;
         // histories at the event cap escape (rare): ended one segment at a time
         for (uint64_t R = __ballot(capped); R != 0;) {
             const int sL = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)R) - 1);
