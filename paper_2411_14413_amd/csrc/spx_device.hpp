@@ -695,9 +695,9 @@ constexpr float CLEAR_MARGIN = 0.02f;
 // word), passed per lane, so lanes of different segments advance together; the test needs
 // the segment's geometry.
 //
-// One diffusive sub-step from block w (the odd or the even half) for a lane where `active`;
-// straight-line code ending in selects, so that inactive lanes keep their state and no
-// branch splits the wave.
+// One diffusive sub-step from block w (the odd or the even half) for a lane where `active`:
+// every lane draws and forms the move; the commit and the hold are written under the lanes'
+// masks, so inactive lanes keep their state.
 __device__ __forceinline__ void diffusive_substep(float lam_l2, uint4 w, bool odd, bool active, Particle<float>& p,
                                                   bool& held)
 {
@@ -710,15 +710,13 @@ __device__ __forceinline__ void diffusive_substep(float lam_l2, uint4 w, bool od
     kahan_try(p.x, p.xc, v, y, t);
     const bool ok = ball_holds(t, p.d, p.r2);
     const bool commit = active && ok, hold = active && !ok;
-    float xn[3] = {p.x[0], p.x[1], p.x[2]}, xcn[3] = {p.xc[0], p.xc[1], p.xc[2]};
-    kahan_commit(xn, xcn, y, t);
+    // the writes under the lanes' masks (cheaper than selecting between old and new values)
+    if (commit) kahan_commit(p.x, p.xc, y, t);
+    if (hold) {
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        p.x[i] = commit ? xn[i] : p.x[i];
-        p.xc[i] = commit ? xcn[i] : p.xc[i];
-        p.d[i] = hold ? dir[i] : p.d[i];
+        for (int i = 0; i < 3; ++i) p.d[i] = dir[i];
+        p.r2 = ell;
     }
-    p.r2 = hold ? ell : p.r2;
     p.e += active ? 1u : 0u;
     p.ndiff += commit ? 1u : 0u;
     held = held || hold;
