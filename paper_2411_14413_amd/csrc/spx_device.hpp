@@ -711,14 +711,17 @@ __device__ __forceinline__ void diffusive_substep(float lam_l2, uint4 w, bool od
     const bool ok = ball_holds(t, p.d, p.r2);
     const bool commit = active && ok, hold = active && !ok;
     // the writes under the lanes' masks (cheaper than selecting between old and new values)
-    if (commit) kahan_commit(p.x, p.xc, y, t);
+    if (commit) {
+        kahan_commit(p.x, p.xc, y, t);
+        ++p.ndiff;
+        ++p.e;
+    }
     if (hold) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) p.d[i] = dir[i];
         p.r2 = ell;
+        ++p.e;
     }
-    p.e += active ? 1u : 0u;
-    p.ndiff += commit ? 1u : 0u;
     held = held || hold;
 }
 
