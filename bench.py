@@ -65,8 +65,8 @@ PEAK_ALU = 256 * 128 * 2.4e9
 # + WRITE_SIZE x 1.000 (KiB per dispatch; factors from a 1 GiB copy and fill).  Valid for the
 # kernels and the workload they were taken on (reported for that workload only); set to None
 # when a kernel changes.
-TRAFFIC = {"k_diffusive32": 320_913 * 1024 * 2.000 + 36_788 * 1024 * 1.000,
-           "k_ballistic32": 1_387 * 1024 * 2.000 + 694_696 * 1024 * 1.000}
+TRAFFIC = {"k_diffusive32": 320_898 * 1024 * 2.000 + 35_621 * 1024 * 1.000,
+           "k_ballistic32": 1_406 * 1024 * 2.000 + 694_911 * 1024 * 1.000}
 
 
 def algorithmic_ops(counters):
