@@ -235,6 +235,18 @@ RECORD_DTYPE = np.dtype([("x", "<f8"), ("y", "<f8"), ("z", "<f8"), ("E", "<f8"),
                          ("bin", "<u4"), ("events", "<u4"), ("diffusive", "<u4"), ("cos_in", "<f8")])
 
 
+def run(configs: Sequence, seed: int = 0, precision: int = 32, params=None, records: bool = False,
+        arrivals: bool = False, autotune: bool = False, stream=None) -> Dict[str, object]:
+    """One transport run of ``configs`` with a plan made for the call: the outputs of
+    Plan.run, plus the plan under "plan" (reuse a Plan to run a sweep several times)."""
+    plan = Plan(configs, params, precision=precision)
+    if autotune and precision == 32:
+        plan.autotune(stream)
+    out = plan.run(seed=seed, records=records, arrivals=arrivals, stream=stream)
+    out["plan"] = plan
+    return out
+
+
 def arrival_edges():
     """Bin edges of the arrival tallies: (energy [61] f64, cos [91] f64, energy f32, cos f32)."""
     e64 = np.empty(N.ARRIVAL_E_BINS + 1)

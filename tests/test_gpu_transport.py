@@ -297,3 +297,15 @@ def test_zero_pressure_measured_launch_against_line_of_sight():
     assert chi2 < dof + 4.5 * math.sqrt(2 * dof)
     assert np.abs(z).max() < 5.0
     assert abs(counts.sum() - exp.sum()) < 4.5 * math.sqrt(exp.sum())
+
+
+def test_run_entry_matches_plan():
+    """The one-call entry gives the tallies of an explicit plan, bit for bit."""
+    cfgs = [si.single_ni(0.5, 20000), si.quaternary(0.9, 30.0, 120.0, [2000, 500, 1500, 800])]
+    say("run(): one-call entry vs Plan.run")
+    a = spx.run(cfgs, seed=5, params=PARAMS)
+    b = spx.Plan(cfgs, PARAMS).run(seed=5)
+    torch.cuda.synchronize()
+    assert np.array_equal(a["counts"].cpu().numpy(), b["counts"].cpu().numpy())
+    assert np.array_equal(a["counters"].cpu().numpy(), b["counters"].cpu().numpy())
+    assert a["plan"].n_segments == 5
