@@ -309,3 +309,20 @@ def test_run_entry_matches_plan():
     assert np.array_equal(a["counts"].cpu().numpy(), b["counts"].cpu().numpy())
     assert np.array_equal(a["counters"].cpu().numpy(), b["counters"].cpu().numpy())
     assert a["plan"].n_segments == 5
+
+
+def test_autotune_leaves_results_unchanged():
+    """Timing runs of the autotuner use their own buffers and the chosen launch parameters do
+    not change any result: tallies, counters and records equal those of the default launch."""
+    cfgs = [si.single_ni(2.0, 20000), si.quaternary(0.5, 25.0, 150.0, [3000, 800, 2000, 1200])]
+    say("autotune: results unchanged")
+    plan = spx.Plan(cfgs, PARAMS)
+    ref = plan.run(seed=9, records=True)
+    torch.cuda.synchronize()
+    r0 = (ref["counts"].cpu().numpy(), ref["counters"].cpu().numpy(), ref["records"].cpu().numpy())
+    launch = plan.autotune()
+    say(f"  chosen {launch}")
+    out = plan.run(seed=9, records=True)
+    torch.cuda.synchronize()
+    for a, b in zip(r0, (out["counts"].cpu().numpy(), out["counters"].cpu().numpy(), out["records"].cpu().numpy())):
+        assert np.array_equal(a, b)
