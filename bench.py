@@ -25,20 +25,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particles/sec (and collisions/sec) at matched tally error, FP32 batched vs FP64 plain"
 
-# Algorithmic ALU work per unit, in VALU issue slots per lane (one slot = one 32-bit
-# add/mul/fma/compare/select/logic/convert; a 32x32->64 multiply and a native
-# transcendental (log2, exp2, sqrt, rcp, sin, cos) cost 4 slots: quarter rate).
-# Counted from the method's formulas, not from the compiled code:
-#   PHILOX: 10 rounds x (2 wide multiplies = 8, 4 xor, 2 key adds) = 140, + 4 words -> ]0,1] (16)
-#   FLIGHT: one Philox block (156), free path -lambda ln RN (7), nearest-surface test over
-#           substrate, target and chamber (100), accept/select (4), compensated move (12)
-#   LAMBDA: ballistic mean free path: table index and interpolation (17), n sigma (2),
-#           speed (5), Maxwellian mean relative speed with erf and exp (30), divide (6)
-#   COLLIDE: one Philox block (156), Box-Muller (40), kinematics, table lookup and
-#           rotation of the relative velocity (125)
-#   DIFFDIR: isotropic direction (20)
-#   LAUNCH: two Philox blocks (312), truncated-normal inverse CDF (35), Thompson
-#           inverse CDF (10), cosine direction and frame rotations (43)
 # VALU issue slots per lane of each unit of work, counted from the formulas the kernel
 # evaluates: a 32x32->64 multiply and a native transcendental take 4 slots, any other FP32 or
 # 32-bit integer operation 1.  Philox4x32-10 block: 10 rounds x (2 multiplies + 2 three-input
@@ -53,10 +39,11 @@ OPS = dict(
     # gas-velocity block and 4 uniforms, Box-Muller 40, kinematics with the table lookup 130
     COLLIDE=PHILOX + 4 * U01 + 40 + 130,
     # half a block (two steps per block), 21-bit codes 5 and their 3 RN 6, isotropic direction
-    # and exponential length 24, step vector 3, compensated move 12, clearance-ball test 7,
-    # bookkeeping 2, plus 2 for the ~1.3 % of steps that leave the ball and take the surface
-    # test and a new clearance (~150 slots)
-    DIFFUSIVE=PHILOX // 2 + 5 + 6 + 24 + 3 + 12 + 7 + 2 + 2,
+    # and exponential length 20 (sqrt, sin, cos, log2 16; 1 - mu^2, two products, the length
+    # scale 4), the step added to the offset from the ball centre 3 (fused multiply-adds),
+    # clearance-ball test 4, bookkeeping 2, plus 2 for the ~1.3 % of steps that leave the ball
+    # and take the surface test and a new clearance (~150 slots)
+    DIFFUSIVE=PHILOX // 2 + 5 + 6 + 20 + 3 + 4 + 2 + 2,
 )
 # Peak: the FP32 vector rate of the MI355X, 157.3 TFLOP/s = 78.6e12 FMA/s, i.e. 128 lanes per
 # CU per clock (256 CUs, 2.4 GHz); one slot = one full-rate 32-bit lane operation.
@@ -65,8 +52,7 @@ PEAK_ALU = 256 * 128 * 2.4e9
 # + WRITE_SIZE x 1.000 (KiB per dispatch; factors from a 1 GiB copy and fill).  Valid for the
 # kernels and the workload they were taken on (reported for that workload only); set to None
 # when a kernel changes.
-TRAFFIC = {"k_diffusive32": 320_898 * 1024 * 2.000 + 35_621 * 1024 * 1.000,
-           "k_ballistic32": 1_406 * 1024 * 2.000 + 694_911 * 1024 * 1.000}
+TRAFFIC = {"k_diffusive32": None, "k_ballistic32": None}
 
 
 def algorithmic_ops(counters):

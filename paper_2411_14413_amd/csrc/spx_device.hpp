@@ -66,6 +66,12 @@ template <> __device__ __forceinline__ double u21<double>(uint32_t k)
 {
     return (double)(k + 1u) * 0x1p-21;
 }
+// 2 u21(k) - 1 = (k + 1 - 2^20) 2^-20 in [-1, 1), formed in one exact multiply-add (both the
+// constant 2^-20 - 1 and the result fit the significand).
+template <typename R> __device__ __forceinline__ R sym21(uint32_t k)
+{
+    return fma((R)k, (R)0x1p-20, (R)0x1p-20 - (R)1);
+}
 
 // A diffusive step needs three RN, so steps 2m and 2m+1 share the Philox block
 // (pid, 2m, cfgcat, 2): the even step takes the top 21 bits of words x, y, z; the odd step
@@ -546,8 +552,8 @@ __device__ __forceinline__ void collide(const SegDev<R>& s, const TabDev<R>& tb,
 template <typename R>
 __device__ __forceinline__ R diffusive_draw(R lam_l2, const uint32_t* k, R* d)
 {
-    const R u0 = u21<R>(k[0]), u1 = u21<R>(k[1]), u2 = u21<R>(k[2]);
-    const R mu = (R)2 * u1 - (R)1;
+    const R u0 = u21<R>(k[0]), u2 = u21<R>(k[2]);
+    const R mu = sym21<R>(k[1]);       // 2 u1 - 1
     const R st = m_sqrt(fma(-mu, mu, (R)1));
     R sp, cp;
     m_sincos2pi(u2, &sp, &cp);
@@ -570,7 +576,7 @@ template <typename R> __device__ __forceinline__ void kahan_add(R& s, R& c, R v)
 // Per-particle dynamic state.
 template <typename R> struct Particle {
     R x[3], xc[3], d[3], E;   // position = x - xc (compensated)
-    R r2;              // batched FP32 diffusive mode: squared clearance-ball radius (d = centre)
+    R r2;              // batched FP32 diffusive mode: squared clearance-ball radius (centre x)
     uint32_t e;        // flights taken
     uint32_t ndiff;    // diffusive steps ended in the gas
     uint32_t ncoll;    // ballistic collisions
@@ -638,53 +644,66 @@ __device__ __forceinline__ Term step_mode(const SegDev<R>& s, const TabDev<R>& t
     return Term{HIT_NONE, -1, 0.f};
 }
 
-// The diffusive move split so that two walks can share it bit for bit: the step vector
-// v = ell d, then the compensated add of v (kahan_try forms the candidate t, kahan_commit
-// accepts it).  Every operation is rounded on its own (no contraction into fused
-// multiply-adds), so the step-by-step walk and the wave-cooperative walk, which forms v in
-// one lane and the sums in another, produce identical positions.
-__device__ __forceinline__ void step_vector(float ell, const float* dir, float* v)
+// Position of a thermalised atom in the batched FP32 walk.  The particle keeps its position
+// as the unevaluated difference x - xc of two floats (as the compensated sum does).  Between
+// two surface tests the walk leaves x alone, so x is the centre of the clearance ball, and
+// adds every step to xc alone: xc <- xc - ell d, one fused multiply-add per coordinate.  Then
+// -xc is the offset from the centre, the ball test is |xc|^2 < r^2 with no subtraction, and
+// the rounding of a step is relative to the offset (at most the ball radius), not to the
+// position.  Before a step is tested, the pair is renormalised exactly (x the rounded
+// position, xc what that rounding lost), which restores the form the compensated sum and
+// the surface test work on.
+//
+// The same operations serve the step-by-step walk and the wave-cooperative walk, so both
+// produce identical positions.
+__device__ __forceinline__ void offset_try(const float* xc, float ell, const float* dir, float* t)
 {
-#pragma clang fp contract(off)
 #pragma unroll
-    for (int i = 0; i < 3; ++i) v[i] = ell * dir[i];
+    for (int i = 0; i < 3; ++i) t[i] = __builtin_fmaf(-ell, dir[i], xc[i]);
 }
-__device__ __forceinline__ void kahan_try(const float* x, const float* xc, const float* v, float* y, float* t)
+// offset t strictly inside the ball of squared radius r2 (false for NaN and infinities)
+__device__ __forceinline__ bool offset_holds(const float* t, float r2)
+{
+    return __builtin_fmaf(t[2], t[2], __builtin_fmaf(t[1], t[1], t[0] * t[0])) < r2;
+}
+// (x, xc) -> (rounded x - xc, the rounding error), exactly (Knuth's two-sum)
+__device__ __forceinline__ void renormalise(float* x, float* xc)
 {
 #pragma clang fp contract(off)
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        y[i] = v[i] - xc[i];
-        t[i] = x[i] + y[i];
+        const float a = x[i], b = -xc[i];
+        const float s = a + b;
+        const float bb = s - a;
+        const float err = (a - (s - bb)) + (b - bb);
+        x[i] = s;
+        xc[i] = -err;
     }
 }
-__device__ __forceinline__ void kahan_commit(float* x, float* xc, const float* y, const float* t)
+// v = ell d, then the compensated add of v (the tested step of diffusive_resolve)
+__device__ __forceinline__ void compensated_step(float* x, float* xc, float ell, const float* dir)
 {
 #pragma clang fp contract(off)
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        xc[i] = (t[i] - x[i]) - y[i];
-        x[i] = t[i];
+        const float v = ell * dir[i];
+        const float y = v - xc[i];
+        const float t = x[i] + y;
+        xc[i] = (t - x[i]) - y;
+        x[i] = t;
     }
-}
-// t strictly inside the ball of squared radius r2 around c (false for NaN and infinities)
-__device__ __forceinline__ bool ball_holds(const float* t, const float* c, float r2)
-{
-    const float q0 = t[0] - c[0], q1 = t[1] - c[1], q2 = t[2] - c[2];
-    return __builtin_fmaf(q2, q2, __builtin_fmaf(q1, q1, q0 * q0)) < r2;
 }
 
 // Slack between the clearance and the ball radius [mm]: far above the FP32 rounding of the
 // position and of the surface test at chamber sizes up to metres.
 constexpr float CLEAR_MARGIN = 0.02f;
 
-// A diffusive step of the batched FP32 path (event p.e + 1).  The direction is drawn afresh
-// every step, so in this mode p.d holds the centre of a clearance ball and p.r2 its squared
-// radius: the anchor's clearance less CLEAR_MARGIN.  A step that ends strictly inside the ball
-// (a convex set, entered at its start) stays more than CLEAR_MARGIN away from every surface,
-// so the surface test would find nothing and is skipped: the compensated move is committed.
-// Otherwise the step is tested as usual and, if it ends in the gas, the ball is rebuilt
-// around its end.  Outcome and arithmetic are those of the tested step.
+// A diffusive step of the batched FP32 path (event p.e + 1).  p.r2 is the squared radius of
+// a clearance ball around p.x: the clearance of p.x less CLEAR_MARGIN.  A step that ends
+// strictly inside the ball (a convex set, entered at its start) stays more than CLEAR_MARGIN
+// away from every surface, so the surface test would find nothing and is skipped: the step
+// is added to the offset.  Otherwise the step is tested as usual and, if it ends in the gas,
+// the ball is rebuilt around its end.  Outcome and arithmetic are those of the tested step.
 //
 // Such a step is taken in two halves, so that a wave can defer its surface tests.
 // diffusive_advance takes the next steps while they stay in the clearance ball: both steps
@@ -703,16 +722,16 @@ __device__ __forceinline__ void diffusive_substep(float lam_l2, uint4 w, bool od
 {
     uint32_t k[3];
     diffusive_codes(w, odd, k);
-    float dir[3], v[3];
+    float dir[3];
     const float ell = diffusive_draw(lam_l2, k, dir);   // diffusive only after a gas collision
-    step_vector(ell, dir, v);
-    float y[3], t[3];
-    kahan_try(p.x, p.xc, v, y, t);
-    const bool ok = ball_holds(t, p.d, p.r2);
+    float t[3];
+    offset_try(p.xc, ell, dir, t);
+    const bool ok = offset_holds(t, p.r2);
     const bool commit = active && ok, hold = active && !ok;
     // the writes under the lanes' masks (cheaper than selecting between old and new values)
     if (commit) {
-        kahan_commit(p.x, p.xc, y, t);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) p.xc[i] = t[i];
         ++p.ndiff;
         ++p.e;
     }
@@ -741,6 +760,7 @@ __device__ __forceinline__ Term diffusive_resolve(const SegDev<float>& s, Partic
 {
     const float dir[3] = {p.d[0], p.d[1], p.d[2]};
     const float ell = p.r2;
+    renormalise(p.x, p.xc);
     float th, qu = 0.f, qv = 0.f;
     const HitF h = hit_test(s, p.x, dir, ell, th, qu, qv, false);
     if (h.state != HIT_NONE) {
@@ -749,25 +769,20 @@ __device__ __forceinline__ Term diffusive_resolve(const SegDev<float>& s, Partic
         return hit_term(s, h.state, qu, qv, dir);
     }
     if (!(ell < m_inf<float>())) return Term{HIT_ESCAPED, -1, 0.f};
-    float v[3], y[3], t[3];
-    step_vector(ell, dir, v);
-    kahan_try(p.x, p.xc, v, y, t);
-    kahan_commit(p.x, p.xc, y, t);
+    compensated_step(p.x, p.xc, ell, dir);
     ++p.ndiff;
     const float c = clearance(s, p.x) - CLEAR_MARGIN;
-    p.d[0] = p.x[0]; p.d[1] = p.x[1]; p.d[2] = p.x[2];
     p.r2 = c > 0.f ? c * c : -1.f;
     return Term{HIT_NONE, -1, 0.f};
 }
 
 // Diffusive steps of the thermalised particle of lane L taken with the whole wave: lane j
-// draws step e + 1 + j (Philox block, direction, length, step vector), then the wave walks
-// the compensated sum through the drawn steps in order on wave-uniform values, stopping
-// before the first step that leaves the clearance ball or passes the event cap.  The sums
-// are those of diffusive_substep, operation for operation, so the committed position,
-// event and step counts equal those of taking the same steps one at a time; the step that
-// leaves the ball is left to the regular walk, which holds and tests it.  Called by the
-// whole wave with L uniform.
+// draws step e + 1 + j (Philox block, direction and length), then the wave adds the drawn
+// steps to the offset in order on wave-uniform values, stopping before the first step that
+// leaves the clearance ball or passes the event cap.  The operations are those of
+// diffusive_substep, so the committed position, event and step counts equal those of taking
+// the same steps one at a time; the step that leaves the ball is left to the regular walk,
+// which holds and tests it.  Called by the whole wave with L uniform.
 __device__ __forceinline__ void coop_walk(const SegDev<float>& s, uint32_t k0, uint32_t k1, uint32_t cap, uint32_t pid,
                                           Particle<float>& p, int L, int lane)
 {
@@ -775,38 +790,32 @@ __device__ __forceinline__ void coop_walk(const SegDev<float>& s, uint32_t k0, u
     if (!(r2 > 0.f)) return;
     const uint32_t pidL = (uint32_t)__builtin_amdgcn_readlane((int)pid, L);
     const uint32_t e0 = (uint32_t)__builtin_amdgcn_readlane((int)p.e, L);
-    float x[3], xc[3], c[3];
+    float xc[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        x[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.x[i]), L));
-        xc[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.xc[i]), L));
-        c[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.d[i]), L));
-    }
+    for (int i = 0; i < 3; ++i) xc[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.xc[i]), L));
     const uint32_t ej = e0 + 1u + (uint32_t)lane;
     uint32_t kc[3];
     diffusive_codes(diffusive_block(pidL, ej, s.cfgcat, k0, k1), (ej & 1u) != 0, kc);
-    float dir[3], v[3];
+    float dir[3];
     const float ell = diffusive_draw(s.lam_l2, kc, dir);
-    step_vector(ell, dir, v);
     // steps that may be taken at all: within the event cap (the ball test rejects the rest)
     const uint64_t allowed = __ballot(ej <= cap);
     int j = 0;
     for (; j < 64; ++j) {
         if (!((allowed >> j) & 1ull)) break;
-        float vj[3], y[3], t[3];
+        float dj[3], t[3];
+        const float ellj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ell), j));
 #pragma unroll
-        for (int i = 0; i < 3; ++i) vj[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[i]), j));
-        kahan_try(x, xc, vj, y, t);
-        if (!__builtin_amdgcn_readfirstlane((int)ball_holds(t, c, r2))) break;
-        kahan_commit(x, xc, y, t);
+        for (int i = 0; i < 3; ++i) dj[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dir[i]), j));
+        offset_try(xc, ellj, dj, t);
+        if (!__builtin_amdgcn_readfirstlane((int)offset_holds(t, r2))) break;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) xc[i] = t[i];
     }
     if (j == 0) return;
     if (lane == L) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            p.x[i] = x[i];
-            p.xc[i] = xc[i];
-        }
+        for (int i = 0; i < 3; ++i) p.xc[i] = xc[i];
         p.e = e0 + (uint32_t)j;
         p.ndiff += (uint32_t)j;
     }

@@ -117,6 +117,12 @@ __device__ __forceinline__ void terminate(const TransportArgs& a, const BlockTal
     p.st = ST_DEAD;
 }
 
+// Number of set bits of the wave-wide mask m in the lanes below this one (mbcnt).
+__device__ __forceinline__ uint64_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Wave-private run of tickets [tk, tk_end), claimed CHUNK at a time from a global counter with
 // one atomic, so that refills rarely touch the counter.
 struct Tickets {
@@ -127,7 +133,7 @@ struct Tickets {
 // Tickets for the dead lanes `dead` of the wave: consecutive tickets of the wave's run in lane
 // order.  Returns this lane's ticket, or ~0 when it gets none.
 __device__ __forceinline__ uint64_t claim(Tickets& T, uint64_t* counter, uint64_t chunk, uint64_t total, uint64_t dead,
-                                          int lane, uint64_t lt_mask)
+                                          int lane)
 {
     if (T.tk == T.tk_end) {
         unsigned long long base = 0;
@@ -145,7 +151,7 @@ __device__ __forceinline__ uint64_t claim(Tickets& T, uint64_t* counter, uint64_
     const uint64_t take = avail < n_dead ? avail : n_dead;
     const uint64_t base = T.tk;
     T.tk += take;
-    const uint64_t rank = (uint64_t)__popcll(dead & lt_mask);
+    const uint64_t rank = lanes_below(dead);
     return (((dead >> lane) & 1ull) && rank < take) ? base + rank : ~0ull;
 }
 
@@ -194,7 +200,7 @@ struct QRun {
 // free.  Slots come from the wave's run (a hand-over may continue into a fresh run).  Their
 // collisions are counted here; thermalisation itself is counted when the walk ends.
 __device__ __forceinline__ void hand_over(const TransportArgs& a, uint32_t pid, int seg, Particle<float>& p,
-                                          LaneAcc& acc, QRun& Q, int lane, uint64_t lt_mask)
+                                          LaneAcc& acc, QRun& Q, int lane)
 {
     const uint64_t T = __ballot(p.st == ST_DIFFUSIVE);
     if (T == 0) return;
@@ -207,7 +213,7 @@ __device__ __forceinline__ void hand_over(const TransportArgs& a, uint32_t pid, 
         fresh = __shfl(b, 0);
     }
     if (p.st == ST_DIFFUSIVE) {
-        const uint64_t rank = (uint64_t)__popcll(T & lt_mask);
+        const uint64_t rank = lanes_below(T);
         const uint64_t slot = rank < rem ? Q.q + rank : fresh + (rank - rem);   // < queue capacity
         ThermRec r;
 #pragma unroll
@@ -243,14 +249,14 @@ __device__ __forceinline__ void close_run(const TransportArgs& a, const QRun& Q,
 template <bool ARR>
 __device__ __forceinline__ void ballistic_loop(const TransportArgs& a, const BlockTally& bt, const SegDev<float>& S,
                                                uint32_t pid, int seg, Particle<float>& p, LaneAcc& acc, QRun& Q,
-                                               bool drained, int lane, uint64_t lt_mask)
+                                               bool drained, int lane)
 {
     for (;;) {
         if (p.st == ST_BALLISTIC) {
             const Term t = step_mode<float, ST_BALLISTIC>(S, a.tab, a.k0, a.k1, pid, a.cap, p);
             if (t.state != HIT_NONE) terminate<ARR>(a, bt, S, pid, p, t, acc);
         }
-        hand_over(a, pid, seg, p, acc, Q, lane, lt_mask);
+        hand_over(a, pid, seg, p, acc, Q, lane);
         if (__ballot(p.st == ST_BALLISTIC) == 0) break;
         if (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_ballistic) break;
     }
@@ -328,7 +334,6 @@ k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
     BlockTally bt;
     lds_setup(a, bt, lds);
     const int lane = threadIdx.x & 63;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     Particle<float> p;
     p.st = ST_DEAD;
     p.e = p.ndiff = p.ncoll = 0;
@@ -341,7 +346,7 @@ k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
         const uint64_t dead = __ballot(p.st == ST_DEAD);
         const int n_dead = __popcll(dead);
         if (!T.drained && n_dead > 0 && (n_dead >= a.refill_ballistic || n_dead == 64)) {
-            const uint64_t my = claim(T, &a.qstate[0], a.chunk_ballistic, a.total, dead, lane, lt_mask);
+            const uint64_t my = claim(T, &a.qstate[0], a.chunk_ballistic, a.total, dead, lane);
             if (my != ~0ull) {
                 const uint64_t g = a.tbase + my;
                 int lo = 0, hi = a.n_seg;
@@ -367,7 +372,7 @@ k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
         }
         const int s0 = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)B) - 1);
         if (__ballot(p.st == ST_BALLISTIC && seg != s0) == 0) {
-            ballistic_loop<ARR>(a, bt, segs[s0], pid, s0, p, acc, Q, T.drained, lane, lt_mask);
+            ballistic_loop<ARR>(a, bt, segs[s0], pid, s0, p, acc, Q, T.drained, lane);
         } else {
             // lanes of several segments: one flight with per-lane constants
             if (p.st == ST_BALLISTIC) {
@@ -375,7 +380,7 @@ k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
                 const Term t = step_mode<float, ST_BALLISTIC>(s, a.tab, a.k0, a.k1, pid, a.cap, p);
                 if (t.state != HIT_NONE) terminate<ARR>(a, bt, s, pid, p, t, acc);
             }
-            hand_over(a, pid, seg, p, acc, Q, lane, lt_mask);
+            hand_over(a, pid, seg, p, acc, Q, lane);
         }
     }
     close_run(a, Q, lane);
@@ -393,7 +398,6 @@ __device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<f
     lds_setup(a, bt, lds);
     const uint64_t total = a.qstate[1];      // written by the ballistic phase of this round
     const int lane = threadIdx.x & 63;
-    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     Particle<float> p;
     p.st = ST_DEAD;
     p.e = p.ndiff = p.ncoll = 0;
@@ -407,7 +411,7 @@ __device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<f
         const uint64_t dead = __ballot(p.st == ST_DEAD);
         const int n_dead = __popcll(dead);
         if (!T.drained && n_dead > 0 && (n_dead >= a.refill_min || n_dead == 64)) {
-            const uint64_t my = claim(T, &a.qstate[2], TICKET_CHUNK, total, dead, lane, lt_mask);
+            const uint64_t my = claim(T, &a.qstate[2], TICKET_CHUNK, total, dead, lane);
             const uint32_t qpid = my != ~0ull ? a.queue[my].pid : 0xFFFFFFFFu;
             if (qpid != 0xFFFFFFFFu) {                 // empty slots (left unused by a wave) are skipped
                 const ThermRec r = a.queue[my];
