@@ -781,13 +781,14 @@ __device__ __forceinline__ Term diffusive_resolve(const SegDev<float>& s, Partic
 // steps to the offset in order on wave-uniform values, stopping before the first step that
 // leaves the clearance ball or passes the event cap.  The operations are those of
 // diffusive_substep, so the committed position, event and step counts equal those of taking
-// the same steps one at a time; the step that leaves the ball is left to the regular walk,
-// which holds and tests it.  Called by the whole wave with L uniform.
+// the same steps one at a time.  The step that leaves the ball (the first one when there is
+// no ball) is then held for the surface test, as diffusive_substep holds it; a step past the
+// cap is not taken, and the history, at the cap, escapes.  Every call therefore takes a step,
+// holds one, or leaves the particle at the cap.  Called by the whole wave with L uniform.
 __device__ __forceinline__ void coop_walk(const SegDev<float>& s, uint32_t k0, uint32_t k1, uint32_t cap, uint32_t pid,
-                                          Particle<float>& p, int L, int lane)
+                                          Particle<float>& p, bool& held, int L, int lane)
 {
     const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.r2), L));
-    if (!(r2 > 0.f)) return;
     const uint32_t pidL = (uint32_t)__builtin_amdgcn_readlane((int)pid, L);
     const uint32_t e0 = (uint32_t)__builtin_amdgcn_readlane((int)p.e, L);
     float xc[3];
@@ -812,12 +813,26 @@ __device__ __forceinline__ void coop_walk(const SegDev<float>& s, uint32_t k0, u
 #pragma unroll
         for (int i = 0; i < 3; ++i) xc[i] = t[i];
     }
-    if (j == 0) return;
+    // the step that ended the run: held unless it is past the cap (or all 64 were taken)
+    const bool hold = j < 64 && ((allowed >> j) & 1ull);
+    float hd[3] = {0.f, 0.f, 0.f}, hl = 0.f;
+    if (hold) {
+        hl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ell), j));
+#pragma unroll
+        for (int i = 0; i < 3; ++i) hd[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dir[i]), j));
+    }
     if (lane == L) {
 #pragma unroll
         for (int i = 0; i < 3; ++i) p.xc[i] = xc[i];
         p.e = e0 + (uint32_t)j;
         p.ndiff += (uint32_t)j;
+        if (hold) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) p.d[i] = hd[i];
+            p.r2 = hl;
+            p.e += 1u;
+            held = true;
+        }
     }
 }
 

@@ -262,6 +262,46 @@ __device__ __forceinline__ void ballistic_loop(const TransportArgs& a, const Blo
     }
 }
 
+// Histories of lanes at the event cap (rare) escape, ended one segment at a time.
+template <bool ARR>
+__device__ __forceinline__ void escape_capped(const TransportArgs& a, const BlockTally& bt,
+                                              const SegDev<float>* __restrict__ segs, int seg, uint32_t pid,
+                                              Particle<float>& p, LaneAcc& acc, bool capped)
+{
+    for (uint64_t R = __ballot(capped); R != 0;) {
+        const int sL = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)R) - 1);
+        const bool mine = capped && seg == sL;
+        R &= ~__ballot(mine);
+        if (mine) {
+            capped = false;
+            terminate<ARR>(a, bt, segs[sL], pid, p, Term{HIT_ESCAPED, -1, 0.f}, acc);
+        }
+    }
+}
+
+// The held steps of the wave (mask H != 0), tested together: with the geometry read once for
+// the wave when they share a segment (the common case), else each lane reading its own.
+template <bool ARR>
+__device__ __forceinline__ void resolve_held(const TransportArgs& a, const BlockTally& bt,
+                                             const SegDev<float>* __restrict__ segs, int seg, uint32_t pid,
+                                             Particle<float>& p, LaneAcc& acc, bool& held, uint64_t H)
+{
+    const int sL = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)H) - 1);
+    if (__ballot(held && seg != sL) == 0) {
+        if (held) {
+            held = false;
+            const SegDev<float>& S = segs[sL];
+            const Term t = diffusive_resolve(S, p);
+            if (t.state != HIT_NONE) terminate<ARR>(a, bt, S, pid, p, t, acc);
+        }
+    } else if (held) {
+        held = false;
+        const SegDev<float>& S = segs[seg];
+        const Term t = diffusive_resolve(S, p);
+        if (t.state != HIT_NONE) terminate<ARR>(a, bt, S, pid, p, t, acc);
+    }
+}
+
 // Diffusive steps of the lanes in segment S with deferred surface tests: a lane whose
 // step leaves its clearance ball holds the step and idles until at least a.defer_min lanes
 // hold one (or every diffusive lane does, or the loop is about to end); then the held
@@ -282,37 +322,13 @@ __device__ __forceinline__ void diffusive_loop(const TransportArgs& a, const Blo
         for (int rep = 0; rep < ADVANCES_PER_CHECK; ++rep)
             if (p.st == ST_DIFFUSIVE && !held && !capped)
                 capped = diffusive_advance(lam_l2, cfgcat, a.k0, a.k1, pid, a.cap, p, held).state != HIT_NONE;
-        // histories at the event cap escape (rare): ended one segment at a time
-        for (uint64_t R = __ballot(capped); R != 0;) {
-            const int sL = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)R) - 1);
-            const bool mine = capped && seg == sL;
-            R &= ~__ballot(mine);
-            if (mine) {
-                capped = false;
-                terminate<ARR>(a, bt, segs[sL], pid, p, Term{HIT_ESCAPED, -1, 0.f}, acc);
-            }
-        }
+        escape_capped<ARR>(a, bt, segs, seg, pid, p, acc, capped);
         const uint64_t H = __ballot(held);
         const uint64_t M = __ballot(p.st == ST_DIFFUSIVE);
         bool stop = M == 0 || (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) ||
                     (drained && __popcll(M) <= COOP_MAX);
         if (H != 0 && (stop || H == M || __popcll(H) >= a.defer_min)) {
-            // the held steps: with the geometry read once for the wave when they share a
-            // segment (the common case), else each lane reading its own
-            const int sL = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)H) - 1);
-            if (__ballot(held && seg != sL) == 0) {
-                if (held) {
-                    held = false;
-                    const SegDev<float>& S = segs[sL];
-                    const Term t = diffusive_resolve(S, p);
-                    if (t.state != HIT_NONE) terminate<ARR>(a, bt, S, pid, p, t, acc);
-                }
-            } else if (held) {
-                held = false;
-                const SegDev<float>& S = segs[seg];
-                const Term t = diffusive_resolve(S, p);
-                if (t.state != HIT_NONE) terminate<ARR>(a, bt, S, pid, p, t, acc);
-            }
+            resolve_held<ARR>(a, bt, segs, seg, pid, p, acc, held, H);
             const uint64_t M2 = __ballot(p.st == ST_DIFFUSIVE);
             stop = M2 == 0 || (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_min) ||
                    (drained && __popcll(M2) <= COOP_MAX);
@@ -443,12 +459,19 @@ __device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<f
             continue;
         }
         // Last walks of a drained wave: each is walked by the whole wave (up to 64 steps per
-        // pass) before the regular steps below.
+        // pass) until its step leaves the ball; then the held steps are tested together.
+        // Every pass takes or holds a step of each walker, or leaves it at the cap, where it
+        // escapes, so the walks end.
         if (T.drained && __popcll(D) <= COOP_MAX) {
+            bool held = false;
             for (uint64_t W = D; W != 0; W &= W - 1) {
                 const int L = __ffsll((unsigned long long)W) - 1;
-                coop_walk(segs[__builtin_amdgcn_readlane(seg, L)], a.k0, a.k1, a.cap, pid, p, L, lane);
+                coop_walk(segs[__builtin_amdgcn_readlane(seg, L)], a.k0, a.k1, a.cap, pid, p, held, L, lane);
             }
+            escape_capped<ARR>(a, bt, segs, seg, pid, p, acc, p.st == ST_DIFFUSIVE && !held && p.e >= a.cap);
+            const uint64_t H = __ballot(held);
+            if (H != 0) resolve_held<ARR>(a, bt, segs, seg, pid, p, acc, held, H);
+            continue;
         }
         diffusive_loop<ARR>(a, bt, segs, seg, lam_l2, cfgcat, pid, p, acc, T.drained);
     }
