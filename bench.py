@@ -52,8 +52,8 @@ PEAK_ALU = 256 * 128 * 2.4e9
 # + WRITE_SIZE x 1.000 (KiB per dispatch; factors from a 1 GiB copy and fill).  Valid for the
 # kernels and the workload they were taken on (reported for that workload only); set to None
 # when a kernel changes.
-TRAFFIC = {"k_diffusive32": 323_760 * 1024 * 2.000 + 50_469 * 1024 * 1.000,
-           "k_ballistic32": 1_408 * 1024 * 2.000 + 693_243 * 1024 * 1.000}
+TRAFFIC = {"k_diffusive32": 323_322 * 1024 * 2.000 + 42_186 * 1024 * 1.000,
+           "k_ballistic32": 1_420 * 1024 * 2.000 + 692_952 * 1024 * 1.000}
 
 
 def algorithmic_ops(counters):
