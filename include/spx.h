@@ -193,7 +193,10 @@ typedef struct spx_plan spx_plan;
  * negative depths, zero weight), E_max <= 0, masses <= 0, an emission law negative somewhere on
  * [0, 90 deg] or with zero integral, non-unit or non-orthogonal axes, an object of unknown kind,
  * with non-positive sizes or outside the chamber, more than 32 absorbing objects in one run,
- * more than 2^24 configurations.  *out is set only on success. */
+ * more than 2^24 configurations.  Device memory: the tables, the segment constants and, for
+ * FP32 plans, a queue of thermalised atoms of 48 B per ticket of a round (the particles run in
+ * equal rounds of at most 2^27 tickets, so at most ~6.4 GB); SPX_ENOMEM if an allocation
+ * fails.  *out is set only on success. */
 int spx_plan_create(const spx_config* h_cfgs, int32_t n_cfgs, const spx_params* h_params, spx_plan** out);
 
 /* Sizes of spx_run's outputs: total tally bins over all segments, counters
