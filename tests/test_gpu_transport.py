@@ -244,6 +244,32 @@ def test_edge_cases():
     assert m["frac"] >= 0.99, m
 
 
+def test_event_cap_in_the_walk():
+    """A cap that ends most 2 Pa histories in the middle of their diffusive walk: every
+    history past it escapes with exactly `cap` events, where the oracle's does, whether the
+    step-by-step walk or the wave-cooperative tail (waves left with few walkers) reaches the
+    cap; records are bit-identical across launch shapes that move histories between the two."""
+    p = si.Params(event_cap=300)
+    cfg = [si.single_ni(2.0, 3000)]
+    say("event cap 300 at 2 Pa")
+    ref = oracle.run(cfg, p, seed=19, records=True)
+    plan = spx.Plan(cfg, p)
+    recs = []
+    for blocks, threads in ((0, 256), (7, 64), (3, 1024)):
+        plan.set_launch(blocks, threads, 4, 16, 8)
+        recs.append(spx.records_to_numpy(plan.run(seed=19, records=True)["records"]))
+        torch.cuda.synchronize()
+    for r in recs[1:]:
+        assert np.array_equal(r, recs[0])
+    rec = recs[0]
+    capped = rec["state"] == 3
+    say(f"  {int(capped.sum())} of {len(rec)} capped; diffusive steps of the capped {int(rec['diffusive'][capped].sum())}")
+    assert capped.mean() > 0.3 and rec["diffusive"][capped].min() > 0
+    assert np.all(rec["events"][capped] == 300) and rec["events"].max() == 300
+    m = match_stats(rec, ref["records"], 1e-3)
+    assert m["same_state"] >= 0.995 and m["frac"] >= 0.99, m
+
+
 def test_phase_times():
     """The two kernels' device times of the last run (events recorded between them)."""
     say("phase times")
