@@ -478,14 +478,15 @@ __device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<f
     lds_flush(a, bt, acc);
 }
 
-// At most 96 VGPRs without the arrival tallies (five waves per SIMD, as the ballistic phase);
-// with them, 128 (four waves), where five would spill.
+// At most 96 VGPRs (five waves per SIMD, as the ballistic phase).  With the arrival tallies
+// a few values spill to scratch at five waves, outside the steps of the walk; that still runs
+// faster than four waves without spills.
 __global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5)))
 k_diffusive32(TransportArgs a, const SegDev<float>* __restrict__ segs)
 {
     diffusive_phase<false>(a, segs);
 }
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5)))
 k_diffusive32_arr(TransportArgs a, const SegDev<float>* __restrict__ segs)
 {
     diffusive_phase<true>(a, segs);
