@@ -195,7 +195,7 @@ typedef struct spx_plan spx_plan;
  * with non-positive sizes or outside the chamber, more than 32 absorbing objects in one run,
  * more than 2^24 configurations.  Device memory: the tables, the segment constants and, for
  * FP32 plans, a queue of thermalised atoms of 48 B per ticket of a round (the particles run in
- * equal rounds of at most 2^27 tickets, so at most ~6.4 GB); SPX_ENOMEM if an allocation
+ * equal rounds of at most 2^28 tickets, so at most ~12.9 GB); SPX_ENOMEM if an allocation
  * fails.  *out is set only on success. */
 int spx_plan_create(const spx_config* h_cfgs, int32_t n_cfgs, const spx_params* h_params, spx_plan** out);
 

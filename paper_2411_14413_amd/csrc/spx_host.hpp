@@ -105,7 +105,7 @@ struct Outputs {
     uint64_t* esum = nullptr;
 };
 
-constexpr uint64_t ROUND_MAX = 1ull << 27;   // tickets per round: a 6.4 GB queue of thermalised atoms
+constexpr uint64_t ROUND_MAX = 1ull << 28;   // tickets per round: a 12.9 GB queue of thermalised atoms
 constexpr uint64_t QUEUE_CHUNK = 64;         // queue slots a wave reserves per atomic
 constexpr uint64_t QUEUE_SLACK_WAVES = 8192;  // waves that may leave slots unused (32 per CU, 256 CUs)
 constexpr size_t LDS_COUNTERS_MAX = 16384;   // bytes: up to 292 segments
