@@ -5,7 +5,9 @@ the same particles.
 
 * three 1e7-particle chambers of the single-target geometry (0.5 / 0 / 2 Pa);
 * the four-cathode Ni/Pd/Pt/Ru system, 2.3e7 particles, 200x200 wafer grid;
-* the 64-chamber sweep of that system (~1.4e8 particles) in one launch.
+* the 64-chamber sweep of that system (~1.4e8 particles) in one launch;
+* that system with 2.7e8 particles, more than one round of the batched path holds (2^28
+  tickets), so the particles run in two rounds.
 """
 import math
 
@@ -134,3 +136,16 @@ def test_fullsize_sweep():
     m, per = _sampled_parity(plan, out, cfgs, 2, 40, np.random.default_rng(2))
     say(f"  sampled parity {m}, worst segment {per.min()}")
     assert m["frac"] >= 0.99 and per.min() >= 0.9
+
+
+def test_fullsize_two_rounds():
+    n = (1 << 28) + (1 << 22)
+    counts = [n * 5 // 23, n * 2 // 23, n * 7 // 23]
+    counts.append(n - sum(counts))
+    cfgs = [si.quaternary(counts=counts)]
+    say(f"full size: four cathodes, {n} particles (two rounds)")
+    plan, out = _run_full(cfgs, seed=4)
+    _check_integer_identities(plan, out)
+    m, per = _sampled_parity(plan, out, cfgs, 4, 400, np.random.default_rng(4))
+    say(f"  sampled parity {m}, per cathode {per}")
+    assert m["frac"] >= 0.99 and per.min() >= 0.98
