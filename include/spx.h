@@ -21,7 +21,13 @@
  *   Every function returns SPX_OK (0) or a negative SPX_E* code; on error the
  *   outputs are unspecified and spx_last_error() describes the failure.  No C++
  *   exception crosses this boundary.  Work is enqueued on `stream`; device-side
- *   faults surface at the next synchronising call.  A plan is not thread-safe.
+ *   faults surface at the next synchronising call.  A plan is not thread-safe: call
+ *   it from one host thread at a time.  Runs of one plan share its queue of
+ *   thermalised atoms and its ticket counters, so each spx_run / spx_run_ex and
+ *   spx_autotune first makes its stream wait for the plan's previous run (an event
+ *   recorded after every run); runs on different streams are therefore executed one
+ *   after the other.  Inside a stream capture that wait and that record are left
+ *   out, and the capturing caller orders the runs of a plan itself.
  *
  * Random numbers: Philox4x32-10, counter (particle, event, (config << 8) | cathode,
  * sub-block), key (seed low word, seed high word); a 32-bit word x gives
@@ -214,9 +220,19 @@ int spx_plan_layout(const spx_plan* plan, uint64_t* h_bin_off, uint64_t* h_first
  *   d_profiles  double[n_bins_total]  counts / (N_seg * bin area), mm^-2 per launched atom; nullable
  *   d_records   spx_record[n_particles_total]; nullable
  * precision 32 runs the whole plan as one persistent launch (replayed from a HIP
- * graph); precision 64 runs one plain FP64 launch per segment.  Asynchronous. */
+ * graph built on the first run and updated in place for new seeds and buffers);
+ * precision 64 runs one plain FP64 launch per segment.  Asynchronous. */
 int spx_run(spx_plan* plan, uint64_t seed, uint64_t* d_counts, uint64_t* d_counters,
             double* d_profiles, spx_record* d_records, void* stream);
+
+/* Graph bookkeeping of an FP32 plan: how many times spx_run / spx_run_ex built and
+ * instantiated the plan's graph, and how many kernel nodes of the instantiated graph had their
+ * arguments replaced.  The graph is rebuilt only when the launch geometry or the set of
+ * non-NULL outputs changes; a new seed or new output buffers replace the arguments of the
+ * affected kernel nodes (hipGraphExecKernelNodeSetParams), after the host has waited for the
+ * plan's previous run to finish (a run with the same seed and buffers does not wait).  Either
+ * pointer may be NULL. */
+int spx_graph_info(const spx_plan* plan, uint64_t* instantiations, uint64_t* node_updates);
 
 /* spx_run with the outputs in a struct, including the arrival tallies (Introduction:
  * energy and angular distributions of arriving particles).  Asynchronous on `stream`;

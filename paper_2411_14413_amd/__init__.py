@@ -208,6 +208,12 @@ class Plan:
                                    int(defer_min)), "spx_set_launch")
         return self.launch
 
+    def graph_info(self):
+        """(graph instantiations, kernel-node argument updates) of this plan so far."""
+        i, u = ctypes.c_uint64(), ctypes.c_uint64()
+        check(lib().spx_graph_info(self._h, ctypes.byref(i), ctypes.byref(u)), "spx_graph_info")
+        return i.value, u.value
+
     def phase_times(self):
         """(ballistic ms, diffusive ms) of the last FP32 run (waits for it)."""
         b, d = ctypes.c_float(), ctypes.c_float()

@@ -403,6 +403,7 @@ static void release(Plan* P)
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     for (hipEvent_t e : P->phase_events) (void)hipEventDestroy(e);
+    if (P->done_event) (void)hipEventDestroy(P->done_event);
     if (P->work_stream) (void)hipStreamDestroy(P->work_stream);
     delete P;
 }
@@ -448,8 +449,9 @@ static int create(const spx_config* cfgs, int n_cfgs, const spx_params* prm, Pla
         return rc == SPX_OK;
     };
     const int ne = prm->table_ne, ns = prm->table_ns, n = P->n_seg;
-    if (hipStreamCreateWithFlags(&P->work_stream, hipStreamNonBlocking) != hipSuccess) {
-        set_error("hipStreamCreate failed");
+    if (hipStreamCreateWithFlags(&P->work_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&P->done_event, hipEventDisableTiming) != hipSuccess) {
+        set_error("hipStreamCreate / hipEventCreate failed");
         release(P);
         return SPX_EDEVICE;
     }
@@ -646,10 +648,35 @@ static int create(const spx_config* cfgs, int n_cfgs, const spx_params* prm, Pla
     return SPX_OK;
 }
 
-// Timing events of the batched path, added to its captured graph (a linear chain of kernel
-// nodes): per round, one event recorded before the ballistic kernel, one between the two
-// kernels and one after the diffusive kernel (spx_phase_times).
-static int add_phase_events(Plan* P, hipGraph_t g)
+// A sink that keeps the launches of a run.
+struct ListSink : LaunchSink {
+    std::vector<KLaunch> L;
+    int put(const KLaunch& k) override
+    {
+        if (k.n_args < 0 || !k.func) {
+            set_error("internal: malformed kernel launch");
+            return SPX_ESTATE;
+        }
+        L.push_back(k);
+        return SPX_OK;
+    }
+};
+
+static Shape plan_shape(const Plan* P)
+{
+    Shape sh;
+    sh.blocks = P->blocks;
+    sh.blocks_diff = P->blocks_diff;
+    sh.threads = P->threads;
+    sh.refill_min = P->refill_min;
+    sh.refill_ballistic = P->refill_ballistic;
+    sh.defer_min = P->defer_min;
+    return sh;
+}
+
+// The graph of a run: its launches as a chain of kernel nodes, with the phase events of each
+// round (recorded before the ballistic kernel, between the kernels and after the diffusive one).
+static int build_graph(Plan* P, const std::vector<KLaunch>& L)
 {
     const size_t n_rounds = (size_t)rounds_of(P->n_tickets);
     while (P->phase_events.size() < 3 * n_rounds) {
@@ -657,90 +684,113 @@ static int add_phase_events(Plan* P, hipGraph_t g)
         SPX_HIP(hipEventCreate(&e));
         P->phase_events.push_back(e);
     }
-    std::vector<hipGraphNode_t> chain;
-    hipGraphNode_t node = nullptr;
-    size_t n = 1;
-    SPX_HIP(hipGraphGetRootNodes(g, &node, &n));
-    while (n == 1) {
-        chain.push_back(node);
-        size_t nd = 0;
-        SPX_HIP(hipGraphNodeGetDependentNodes(node, nullptr, &nd));
-        if (nd > 1) break;
-        if (nd == 1) SPX_HIP(hipGraphNodeGetDependentNodes(node, &node, &nd));
-        n = nd;
+    if (P->graph_exec) {
+        SPX_HIP(hipGraphExecDestroy(P->graph_exec));
+        P->graph_exec = nullptr;
     }
-    size_t r = 0;
-    for (size_t i = 0; i + 1 < chain.size() && r < n_rounds; ++i) {
-        hipGraphNodeType ty;
-        SPX_HIP(hipGraphNodeGetType(chain[i], &ty));
-        if (ty != hipGraphNodeTypeKernel) continue;
+    if (P->graph) {
+        SPX_HIP(hipGraphDestroy(P->graph));
+        P->graph = nullptr;
+    }
+    P->graph_launches.clear();
+    P->graph_nodes.clear();
+    hipGraph_t g = nullptr;
+    SPX_HIP(hipGraphCreate(&g, 0));
+    P->graph = g;
+    hipGraphNode_t prev = nullptr;
+    size_t round = 0;
+    auto chain_event = [&](hipEvent_t e) -> int {
+        hipGraphNode_t n = nullptr;
+        SPX_HIP(hipGraphAddEventRecordNode(&n, g, prev ? &prev : nullptr, prev ? 1 : 0, e));
+        prev = n;
+        return SPX_OK;
+    };
+    for (const KLaunch& k : L) {
+        if (k.phase == 1) {
+            if (round >= n_rounds) {
+                set_error("internal: more rounds in the run than in the plan");
+                return SPX_ESTATE;
+            }
+            SPX_TRY(chain_event(P->phase_events[3 * round]));
+        }
+        void* args[8];
+        k.pointers(args);
         hipKernelNodeParams kp{};
-        SPX_HIP(hipGraphKernelNodeGetParams(chain[i], &kp));
-        if (!is_ballistic_kernel(kp.func) || i == 0) continue;
-        const hipGraphNode_t prev = chain[i - 1], bal = chain[i], dif = chain[i + 1];
-        hipGraphNode_t e0, e1, e2;
-        SPX_HIP(hipGraphAddEventRecordNode(&e0, g, &prev, 1, P->phase_events[3 * r]));
-        SPX_HIP(hipGraphAddDependencies(g, &e0, &bal, 1));
-        SPX_HIP(hipGraphAddEventRecordNode(&e1, g, &bal, 1, P->phase_events[3 * r + 1]));
-        SPX_HIP(hipGraphAddDependencies(g, &e1, &dif, 1));
-        SPX_HIP(hipGraphAddEventRecordNode(&e2, g, &dif, 1, P->phase_events[3 * r + 2]));
-        if (i + 2 < chain.size()) SPX_HIP(hipGraphAddDependencies(g, &e2, &chain[i + 2], 1));
-        ++r;
+        kp.func = const_cast<void*>(k.func);
+        kp.gridDim = k.grid;
+        kp.blockDim = k.block;
+        kp.sharedMemBytes = k.smem;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        hipGraphNode_t n = nullptr;
+        SPX_HIP(hipGraphAddKernelNode(&n, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        prev = n;
+        P->graph_launches.push_back(k);
+        P->graph_nodes.push_back(n);
+        if (k.phase == 1) SPX_TRY(chain_event(P->phase_events[3 * round + 1]));
+        if (k.phase == 2) SPX_TRY(chain_event(P->phase_events[3 * round++ + 2]));
     }
-    if (r != n_rounds) {
-        set_error("internal: unexpected shape of the transport graph");
+    if (round != n_rounds) {
+        set_error("internal: unexpected number of rounds in the transport graph");
         return SPX_ESTATE;
     }
+    SPX_HIP(hipGraphInstantiate(&P->graph_exec, g, nullptr, nullptr, 0));
+    ++P->graph_instantiations;
     return SPX_OK;
 }
 
+// A run of the batched path replays the plan's graph.  The graph is built once per launch
+// geometry and set of outputs; a new seed or new output buffers only replace the arguments of
+// the kernel nodes in the instantiated graph.
 static int run(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st)
 {
-    if (P->params.precision == 64) return launch_transport64(P, seed, o, st);
-    GraphKey key;
-    key.seed = seed;
-    key.counts = o.counts;
-    key.counters = o.counters;
-    key.profiles = o.profiles;
-    key.records = o.records;
-    key.arr_E = o.arr_E;
-    key.arr_A = o.arr_A;
-    key.esum = o.esum;
-    key.blocks = P->blocks;
-    key.threads = P->threads;
-    key.refill = P->refill_min;
-    key.refill_b = P->refill_ballistic;
-    key.defer = P->defer_min;
-    if (!P->graph_exec || !(key == P->graph_key)) {
-        if (P->graph_exec) {
-            SPX_HIP(hipGraphExecDestroy(P->graph_exec));
-            P->graph_exec = nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    SPX_HIP(hipStreamIsCapturing(st, &cs));
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    // runs on other streams share the plan's queue and counters: wait for the last one
+    if (P->done_recorded && !capturing) SPX_HIP(hipStreamWaitEvent(st, P->done_event, 0));
+    if (P->params.precision == 64) {
+        SPX_TRY(launch_transport64(P, seed, o, st));
+    } else {
+        QueueMem q;
+        q.queue = P->d_queue;
+        q.cap = P->queue_cap;
+        q.qstate = P->d_qstate;
+        ListSink ls;
+        SPX_TRY(build_transport32(P, seed, o, P->d_tfirst, P->n_tickets, plan_shape(P), q, ls));
+        bool same = P->graph_exec && ls.L.size() == P->graph_launches.size();
+        for (size_t i = 0; same && i < ls.L.size(); ++i) same = ls.L[i].same_shape(P->graph_launches[i]);
+        if (!same) {
+            SPX_TRY(build_graph(P, ls.L));
+        } else {
+            // an instantiated graph may keep its kernel arguments in device memory: replace them
+            // only once the previous launch of the graph has finished
+            bool waited = false;
+            for (size_t i = 0; i < ls.L.size(); ++i) {
+                if (ls.L[i].same_args(P->graph_launches[i])) continue;
+                if (!waited && P->done_recorded) SPX_HIP(hipEventSynchronize(P->done_event));
+                waited = true;
+                const KLaunch& k = ls.L[i];
+                void* args[8];
+                k.pointers(args);
+                hipKernelNodeParams kp{};
+                kp.func = const_cast<void*>(k.func);
+                kp.gridDim = k.grid;
+                kp.blockDim = k.block;
+                kp.sharedMemBytes = k.smem;
+                kp.kernelParams = args;
+                kp.extra = nullptr;
+                SPX_HIP(hipGraphExecKernelNodeSetParams(P->graph_exec, P->graph_nodes[i], &kp));
+                P->graph_launches[i] = k;
+                ++P->graph_updates;
+            }
         }
-        if (P->graph) {
-            SPX_HIP(hipGraphDestroy(P->graph));
-            P->graph = nullptr;
-        }
-        SPX_HIP(hipStreamBeginCapture(P->work_stream, hipStreamCaptureModeThreadLocal));
-        const int rc = launch_transport32(P, seed, o, P->work_stream, P->d_tfirst, P->n_tickets, P->blocks,
-                                          P->blocks_diff, P->threads, P->refill_min, P->refill_ballistic,
-                                          P->defer_min, nullptr);
-        hipGraph_t g = nullptr;
-        const hipError_t ec = hipStreamEndCapture(P->work_stream, &g);
-        if (rc != SPX_OK) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc;
-        }
-        SPX_HIP(ec);
-        const int rt = add_phase_events(P, g);
-        if (rt != SPX_OK) {
-            (void)hipGraphDestroy(g);
-            return rt;
-        }
-        P->graph = g;
-        SPX_HIP(hipGraphInstantiate(&P->graph_exec, P->graph, nullptr, nullptr, 0));
-        P->graph_key = key;
+        SPX_HIP(hipGraphLaunch(P->graph_exec, st));
     }
-    SPX_HIP(hipGraphLaunch(P->graph_exec, st));
+    if (!capturing) {
+        SPX_HIP(hipEventRecord(P->done_event, st));
+        P->done_recorded = true;
+    }
     return SPX_OK;
 }
 
@@ -754,6 +804,13 @@ static int autotune(Plan* P, hipStream_t st)
     // launch ends in a tail of the longest histories whose share of the time shrinks with the
     // work per lane, and a sample with too little work per lane favours shapes that only
     // shorten that tail.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    SPX_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) {
+        set_error("spx_autotune cannot run inside a stream capture (it times and synchronises)");
+        return SPX_ESTATE;
+    }
+    if (P->done_recorded) SPX_HIP(hipStreamWaitEvent(st, P->done_event, 0));
     int bpc_max = 0, bpc_dmax = 0;
     SPX_TRY(occupancy_transport32(P, 256, &bpc_max, &bpc_dmax));
     const double lanes = (double)std::max(1, bpc_max) * P->n_cu * 256.0;
@@ -784,8 +841,19 @@ static int autotune(Plan* P, hipStream_t st)
             Outputs to;
             to.counts = d_counts;
             to.counters = d_ctr;
-            if (rc == SPX_OK)
-                rc = launch_transport32(P, 0x5eed, to, st, d_tf, tf[n], blocks, blocks_d, t, rmin, rbal, defer, nullptr);
+            Shape sh;
+            sh.blocks = blocks;
+            sh.blocks_diff = blocks_d;
+            sh.threads = t;
+            sh.refill_min = rmin;
+            sh.refill_ballistic = rbal;
+            sh.defer_min = defer;
+            QueueMem q;
+            q.queue = P->d_queue;
+            q.cap = P->queue_cap;
+            q.qstate = P->d_qstate;
+            StreamSink ss(st, nullptr);
+            if (rc == SPX_OK) rc = build_transport32(P, 0x5eed, to, d_tf, tf[n], sh, q, ss);
             if (rc == SPX_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
                 rc = SPX_EDEVICE;
             float ms = 0.f;
@@ -1069,6 +1137,14 @@ int spx_phase_times(spx_plan* P, float* ms_ballistic, float* ms_diffusive)
     }
     *ms_ballistic = b;
     *ms_diffusive = d;
+    return SPX_OK;
+}
+
+int spx_graph_info(const spx_plan* P, uint64_t* instantiations, uint64_t* node_updates)
+{
+    if (!P) return fail("null plan");
+    if (instantiations) *instantiations = P->graph_instantiations;
+    if (node_updates) *node_updates = P->graph_updates;
     return SPX_OK;
 }
 

@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/spx.h"
@@ -124,22 +126,65 @@ constexpr int COOP_MAX = 8;                   // drained waves with at most this
 constexpr size_t LDS_TALLY_MAX = 49152;      // bytes: up to 12288 bins
 constexpr size_t LDS_ARRIVALS_MAX = 4096;     // bytes: arrival histograms of up to 6 segments
 
-struct GraphKey {
-    uint64_t seed = 0;
-    void* counts = nullptr;
-    void* counters = nullptr;
-    void* profiles = nullptr;
-    void* records = nullptr;
-    void* arr_E = nullptr;
-    void* arr_A = nullptr;
-    void* esum = nullptr;
-    int blocks = 0, threads = 0, refill = 0, refill_b = 0, defer = 0;
-    bool operator==(const GraphKey& o) const
+// One kernel launch of a run with its arguments stored by value.  A run of the batched path
+// is a list of these: enqueued on a stream as they are made, or made into the kernel nodes of
+// a graph whose arguments can later be replaced in the instantiated graph (a new seed or new
+// output buffers then need no new graph).
+struct KLaunch {
+    const void* func = nullptr;
+    dim3 grid{1, 1, 1}, block{1, 1, 1};
+    uint32_t smem = 0;
+    int phase = 0;              // 1: the ballistic kernel of a round, 2: its diffusive kernel, else 0
+    int n_args = 0;
+    uint16_t off[8] = {};
+    uint16_t last_size = 0;
+    alignas(16) unsigned char buf[384] = {};
+
+    template <typename T> void arg(const T& v)
     {
-        return seed == o.seed && counts == o.counts && counters == o.counters && profiles == o.profiles &&
-               records == o.records && arr_E == o.arr_E && arr_A == o.arr_A && esum == o.esum && blocks == o.blocks &&
-               threads == o.threads && refill == o.refill && refill_b == o.refill_b && defer == o.defer;
+        static_assert(std::is_trivially_copyable<T>::value, "kernel arguments are copied bytewise");
+        size_t o = n_args ? (size_t)off[n_args - 1] + last_size : 0;
+        o = (o + alignof(T) - 1) / alignof(T) * alignof(T);
+        if (n_args >= 8 || o + sizeof(T) > sizeof(buf)) {
+            n_args = -1;              // reported by the sinks: never launched
+            return;
+        }
+        std::memcpy(buf + o, &v, sizeof(T));
+        off[n_args++] = (uint16_t)o;
+        last_size = (uint16_t)sizeof(T);
     }
+    // pointers to the stored arguments, as hipLaunchKernel and graph kernel nodes take them
+    void pointers(void** p) const
+    {
+        for (int i = 0; i < n_args; ++i) p[i] = const_cast<unsigned char*>(buf) + off[i];
+    }
+    // same kernel and launch geometry (the arguments may differ)
+    bool same_shape(const KLaunch& o) const
+    {
+        return func == o.func && grid.x == o.grid.x && block.x == o.block.x && smem == o.smem && phase == o.phase &&
+               n_args == o.n_args;
+    }
+    bool same_args(const KLaunch& o) const { return std::memcmp(buf, o.buf, sizeof(buf)) == 0; }
+};
+
+// Receiver of the launches of a run, in order.
+struct LaunchSink {
+    virtual int put(const KLaunch& k) = 0;
+    virtual ~LaunchSink() = default;
+};
+
+// Launch geometry and thresholds of the two persistent transport kernels.
+struct Shape {
+    int blocks = 0, blocks_diff = 0, threads = 256, refill_min = 8, refill_ballistic = 8, defer_min = DEFER_MIN;
+};
+
+// Queue of thermalised atoms and ticket counters a run works in: the plan's own allocation, or
+// caller-independent static scratch.  Rounds hold at most round_max tickets.
+struct QueueMem {
+    ThermRec* queue = nullptr;
+    uint64_t cap = 0;            // slots
+    uint64_t* qstate = nullptr;  // 3 counters
+    uint64_t round_max = ROUND_MAX;
 };
 
 }  // namespace spx
@@ -183,7 +228,14 @@ struct spx_plan {
 
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
-    spx::GraphKey graph_key;
+    std::vector<spx::KLaunch> graph_launches;   // the kernel nodes' launches, in graph order
+    std::vector<hipGraphNode_t> graph_nodes;     // ... and their nodes
+    uint64_t graph_instantiations = 0;           // graphs built and instantiated
+    uint64_t graph_updates = 0;                  // kernel nodes whose arguments were replaced
+    // stream order between runs on different streams: recorded after each run, waited for by
+    // the next run or autotune (all of them share the plan's queue and ticket counters)
+    hipEvent_t done_event = nullptr;
+    bool done_recorded = false;
 };
 
 namespace spx {
@@ -191,11 +243,20 @@ using Plan = spx_plan;
 int build_tables(Plan* P);
 // events (nullable, not while capturing): 3 per round, recorded at the round's start, after
 // its ballistic phase and after its diffusive phase.
-int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st, const uint64_t* tfirst,
-                       uint64_t total, int blocks, int blocks_diff, int threads, int refill_min, int refill_ballistic,
-                       int defer_min, const hipEvent_t* events);
-uint64_t rounds_of(uint64_t total);
-bool is_ballistic_kernel(const void* f);
+// The launches of one batched FP32 run over tickets [0, total) of `tfirst` in rounds of at most
+// q.round_max tickets: zero the outputs, per round reset / ballistic / diffusive, normalise.
+int build_transport32(Plan* P, uint64_t seed, const Outputs& o, const uint64_t* tfirst, uint64_t total,
+                      const Shape& sh, const QueueMem& q, LaunchSink& sink);
+// A sink that launches on `st`; with `events` (3 per round, not while capturing) it records one
+// before each ballistic kernel, one after it and one after the diffusive kernel.
+struct StreamSink : LaunchSink {
+    hipStream_t st;
+    const hipEvent_t* events;
+    size_t round = 0;
+    StreamSink(hipStream_t s, const hipEvent_t* e) : st(s), events(e) {}
+    int put(const KLaunch& k) override;
+};
+uint64_t rounds_of(uint64_t total, uint64_t round_max = ROUND_MAX);
 int launch_transport64(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st);
 // Arrival bin edges in double (as the comparator uses them); the batched path rounds them to float.
 void arrival_edges(double* e_edges, double* c_edges);

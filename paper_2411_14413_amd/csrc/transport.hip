@@ -574,35 +574,60 @@ __global__ void k_normalize(const unsigned long long* __restrict__ counts, const
     }
 }
 
-static int zero_u64(uint64_t* p, uint64_t n, hipStream_t st)
+static int zero_u64(uint64_t* p, uint64_t n, LaunchSink& sink)
 {
     if (!p || n == 0) return SPX_OK;
-    const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 + 1 : 4096);
-    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, st, (unsigned long long*)p, n, (unsigned long long*)nullptr,
-                       (uint64_t)0);
-    SPX_HIP(hipGetLastError());
-    return SPX_OK;
+    KLaunch k;
+    k.func = (const void*)k_zero;
+    k.grid = dim3((unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 + 1 : 4096));
+    k.block = dim3(256);
+    k.arg((unsigned long long*)p);
+    k.arg(n);
+    k.arg((unsigned long long*)nullptr);
+    k.arg((uint64_t)0);
+    return sink.put(k);
 }
 
-static int launch_zero(Plan* P, const Outputs& o, hipStream_t st)
+static int put_zero(Plan* P, const Outputs& o, LaunchSink& sink)
 {
-    SPX_TRY(zero_u64(o.counts, P->n_bins_total, st));
-    SPX_TRY(zero_u64(o.counters, (uint64_t)P->n_seg * N_COUNTERS, st));
+    SPX_TRY(zero_u64(o.counts, P->n_bins_total, sink));
+    SPX_TRY(zero_u64(o.counters, (uint64_t)P->n_seg * N_COUNTERS, sink));
     if (o.arr_E) {
-        SPX_TRY(zero_u64(o.arr_E, (uint64_t)P->n_seg * SPX_ARRIVAL_E_BINS, st));
-        SPX_TRY(zero_u64(o.arr_A, (uint64_t)P->n_seg * SPX_ARRIVAL_A_BINS, st));
-        SPX_TRY(zero_u64(o.esum, P->n_bins_total, st));
+        SPX_TRY(zero_u64(o.arr_E, (uint64_t)P->n_seg * SPX_ARRIVAL_E_BINS, sink));
+        SPX_TRY(zero_u64(o.arr_A, (uint64_t)P->n_seg * SPX_ARRIVAL_A_BINS, sink));
+        SPX_TRY(zero_u64(o.esum, P->n_bins_total, sink));
     }
     return SPX_OK;
 }
 
-static int launch_normalize(Plan* P, const uint64_t* d_counts, double* d_profiles, hipStream_t st)
+static int put_normalize(Plan* P, const uint64_t* d_counts, double* d_profiles, LaunchSink& sink)
 {
     const uint64_t n = P->n_bins_total;
-    const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 + 1 : 4096);
-    hipLaunchKernelGGL(k_normalize, dim3(blocks), dim3(256), 0, st, (const unsigned long long*)d_counts,
-                       P->d_bin_off, P->d_seg_norm, P->n_seg, n, d_profiles);
-    SPX_HIP(hipGetLastError());
+    KLaunch k;
+    k.func = (const void*)k_normalize;
+    k.grid = dim3((unsigned)((n + 255) / 256 < 4096 ? (n + 255) / 256 + 1 : 4096));
+    k.block = dim3(256);
+    k.arg((const unsigned long long*)d_counts);
+    k.arg((const uint64_t*)P->d_bin_off);
+    k.arg((const double*)P->d_seg_norm);
+    k.arg((int)P->n_seg);
+    k.arg(n);
+    k.arg(d_profiles);
+    return sink.put(k);
+}
+
+int StreamSink::put(const KLaunch& k)
+{
+    if (k.n_args < 0 || !k.func) {
+        set_error("internal: malformed kernel launch");
+        return SPX_ESTATE;
+    }
+    if (events && k.phase == 1) SPX_HIP(hipEventRecord(events[3 * round], st));
+    void* args[8];
+    k.pointers(args);
+    SPX_HIP(hipLaunchKernel(k.func, k.grid, k.block, args, k.smem, st));
+    if (events && k.phase == 1) SPX_HIP(hipEventRecord(events[3 * round + 1], st));
+    if (events && k.phase == 2) SPX_HIP(hipEventRecord(events[3 * round++ + 2], st));
     return SPX_OK;
 }
 
@@ -631,21 +656,18 @@ int occupancy_transport32(const Plan* P, int threads, int* bpc_ballistic, int* b
     return SPX_OK;
 }
 
-// The batched kernels' entry points, to find their nodes in a captured graph.
-bool is_ballistic_kernel(const void* f)
+// Rounds of a ticket space of `total` tickets: as few as round_max allows, of equal size.
+uint64_t rounds_of(uint64_t total, uint64_t round_max)
 {
-    return f == (const void*)k_ballistic32<false> || f == (const void*)k_ballistic32<true>;
+    return total == 0 ? 0 : (total + round_max - 1) / round_max;
 }
 
-// Rounds of a ticket space of `total` tickets: as few as ROUND_MAX allows, of equal size.
-uint64_t rounds_of(uint64_t total) { return total == 0 ? 0 : (total + ROUND_MAX - 1) / ROUND_MAX; }
-
-int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st, const uint64_t* tfirst,
-                       uint64_t total, int blocks, int blocks_diff, int threads, int refill_min, int refill_ballistic,
-                       int defer_min, const hipEvent_t* events)
+int build_transport32(Plan* P, uint64_t seed, const Outputs& o, const uint64_t* tfirst, uint64_t total,
+                      const Shape& sh, const QueueMem& q, LaunchSink& sink)
 {
-    SPX_TRY(launch_zero(P, o, st));
+    SPX_TRY(put_zero(P, o, sink));
     TransportArgs a;
+    std::memset(&a, 0, sizeof(a));     // padding too: launches are compared bytewise
     a.segs = P->d_seg32;
     a.tab.theta = P->d_theta32;
     a.tab.betamax = P->d_betamax32;
@@ -654,8 +676,8 @@ int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st,
     a.tab.xs = (float)((P->params.table_ne - 1) / ((P->params.log_eps_hi - P->params.log_eps_lo) * 3.321928094887362));
     a.tfirst = tfirst;
     a.torder = P->d_torder;
-    a.queue = P->d_queue;
-    a.qstate = P->d_qstate;
+    a.queue = q.queue;
+    a.qstate = q.qstate;
     a.counts = (unsigned long long*)o.counts;
     a.counters = (unsigned long long*)o.counters;
     a.records = o.records;
@@ -668,29 +690,30 @@ int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st,
     a.k1 = (uint32_t)(seed >> 32);
     a.cap = P->params.event_cap;
     a.n_seg = P->n_seg;
-    a.refill_min = refill_min;
-    a.refill_ballistic = refill_ballistic;
-    a.defer_min = defer_min;
+    a.refill_min = sh.refill_min;
+    a.refill_ballistic = sh.refill_ballistic;
+    a.defer_min = sh.defer_min;
     a.n_bins = (uint32_t)P->n_bins_total;
     bool lc, lt, la;
     const size_t smem = transport32_lds(P, o.arr_E != nullptr, &lc, &lt, &la);
-    int blocks_diff_arr = blocks_diff;
+    int blocks_diff_arr = sh.blocks_diff;
     if (o.arr_E) {
         int bpc_arr = 0;
-        SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc_arr, k_diffusive32_arr, threads, smem));
-        if (bpc_arr > 0) blocks_diff_arr = std::min(blocks_diff, bpc_arr * P->n_cu);
+        SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc_arr, k_diffusive32_arr, sh.threads, smem));
+        if (bpc_arr > 0) blocks_diff_arr = std::min(sh.blocks_diff, bpc_arr * P->n_cu);
     }
     a.lds_counters = lc ? 1 : 0;
     a.lds_tally = lt ? 1 : 0;
     a.lds_arrivals = la ? 1 : 0;
-    const uint64_t n_rounds = rounds_of(total);
+    const uint64_t n_rounds = rounds_of(total, q.round_max);
     const uint64_t per_round = n_rounds ? (total + n_rounds - 1) / n_rounds : 0;
     // every queue slot a round can reserve: its atoms plus at most one unused run per wave
-    const uint64_t waves = (uint64_t)blocks * (uint64_t)((threads + 63) / 64);
-    if (n_rounds && per_round + waves * QUEUE_CHUNK > P->queue_cap) {
+    const uint64_t waves = (uint64_t)sh.blocks * (uint64_t)((sh.threads + 63) / 64);
+    if (n_rounds && per_round + waves * QUEUE_CHUNK > q.cap) {
         set_error("internal: round larger than the thermalisation queue");
         return SPX_ESTATE;
     }
+    const SegDev<float>* segs = P->d_seg32;
     for (uint64_t r = 0; r < n_rounds; ++r) {
         a.tbase = r * per_round;
         a.total = (a.tbase + per_round < total) ? per_round : total - a.tbase;
@@ -699,32 +722,39 @@ int launch_transport32(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st,
         uint64_t cb = TICKET_CHUNK;
         while (2 * cb <= TICKET_CHUNK_BALLISTIC_MAX && 2 * cb * 4 * waves <= a.total) cb *= 2;
         a.chunk_ballistic = (uint32_t)cb;
-        if (events) SPX_HIP(hipEventRecord(events[3 * r], st));
-        hipLaunchKernelGGL(k_round_reset, dim3(1), dim3(64), 0, st, P->d_qstate);
-        SPX_HIP(hipGetLastError());
-        if (a.arr_E)
-            hipLaunchKernelGGL(k_ballistic32<true>, dim3(blocks), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
-        else
-            hipLaunchKernelGGL(k_ballistic32<false>, dim3(blocks), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
-        SPX_HIP(hipGetLastError());
-        if (events) SPX_HIP(hipEventRecord(events[3 * r + 1], st));
-        if (a.arr_E) {
-            // the instance with the tallies has its own resident limit (fewer waves per SIMD)
-            hipLaunchKernelGGL(k_diffusive32_arr, dim3(blocks_diff_arr), dim3(threads), smem, st, a,
-                               (const SegDev<float>*)P->d_seg32);
-        } else {
-            hipLaunchKernelGGL(k_diffusive32, dim3(blocks_diff), dim3(threads), smem, st, a, (const SegDev<float>*)P->d_seg32);
-        }
-        SPX_HIP(hipGetLastError());
-        if (events) SPX_HIP(hipEventRecord(events[3 * r + 2], st));
+        KLaunch reset;
+        reset.func = (const void*)k_round_reset;
+        reset.block = dim3(64);
+        reset.arg(q.qstate);
+        SPX_TRY(sink.put(reset));
+        KLaunch bal;
+        bal.func = a.arr_E ? (const void*)k_ballistic32<true> : (const void*)k_ballistic32<false>;
+        bal.grid = dim3((unsigned)sh.blocks);
+        bal.block = dim3((unsigned)sh.threads);
+        bal.smem = (uint32_t)smem;
+        bal.phase = 1;
+        bal.arg(a);
+        bal.arg(segs);
+        SPX_TRY(sink.put(bal));
+        // the instance with the arrival tallies has its own resident limit (fewer waves per SIMD)
+        KLaunch dif;
+        dif.func = a.arr_E ? (const void*)k_diffusive32_arr : (const void*)k_diffusive32;
+        dif.grid = dim3((unsigned)(a.arr_E ? blocks_diff_arr : sh.blocks_diff));
+        dif.block = dim3((unsigned)sh.threads);
+        dif.smem = (uint32_t)smem;
+        dif.phase = 2;
+        dif.arg(a);
+        dif.arg(segs);
+        SPX_TRY(sink.put(dif));
     }
-    if (o.profiles) SPX_TRY(launch_normalize(P, o.counts, o.profiles, st));
+    if (o.profiles) SPX_TRY(put_normalize(P, o.counts, o.profiles, sink));
     return SPX_OK;
 }
 
 int launch_transport64(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st)
 {
-    SPX_TRY(launch_zero(P, o, st));
+    StreamSink sink(st, nullptr);
+    SPX_TRY(put_zero(P, o, sink));
     TabDev<double> tab;
     tab.theta = P->d_theta64;
     tab.betamax = P->d_betamax64;
@@ -747,7 +777,7 @@ int launch_transport64(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st)
                            o.records, arr);
         SPX_HIP(hipGetLastError());
     }
-    if (o.profiles) SPX_TRY(launch_normalize(P, o.counts, o.profiles, st));
+    if (o.profiles) SPX_TRY(put_normalize(P, o.counts, o.profiles, sink));
     return SPX_OK;
 }
 

@@ -386,3 +386,51 @@ def test_autotune_leaves_results_unchanged():
     torch.cuda.synchronize()
     for a, b in zip(r0, (out["counts"].cpu().numpy(), out["counters"].cpu().numpy(), out["records"].cpu().numpy())):
         assert np.array_equal(a, b)
+
+
+def test_seeds_share_one_graph():
+    """Five seeds, each into fresh output buffers, through one instantiated graph: the seed and
+    the buffers are replaced in the graph's kernel nodes, the graph is built once, and every
+    run equals a fresh plan's run of the same seed bit for bit."""
+    cfgs = [si.single_ni(0.5, 20000), si.single_ni(2.0, 2000), si.quaternary(0.9, 30.0, 120.0, [2000, 500, 1500, 800])]
+    say("five seeds through one graph")
+    plan = spx.Plan(cfgs, PARAMS)
+    outs = []
+    for seed in (3, 4, 5, 2**40 + 7, 3):
+        o = plan.run(seed=seed, records=True)
+        outs.append((seed, o))
+    torch.cuda.synchronize()
+    inst, upd = plan.graph_info()
+    say(f"  instantiations {inst}, node updates {upd}")
+    assert inst == 1
+    assert upd >= 4 * 3          # at least the zero, ballistic and diffusive nodes of each later run
+    for seed, o in outs:
+        f = spx.Plan(cfgs, PARAMS).run(seed=seed, records=True)
+        torch.cuda.synchronize()
+        for key in ("counts", "counters", "records", "profiles"):
+            assert torch.equal(o[key], f[key]), (seed, key)
+    assert not torch.equal(outs[0][1]["counts"], outs[1][1]["counts"])
+    assert torch.equal(outs[0][1]["records"], outs[4][1]["records"])
+    # a new set of outputs (no records) needs a graph of its own
+    plan.run(seed=3, records=False)
+    torch.cuda.synchronize()
+    assert plan.graph_info()[0] == 2
+
+
+def test_runs_on_two_streams_are_ordered():
+    """Runs of one plan on two streams, enqueued back to back without host synchronisation,
+    share the plan's queue and counters; the library orders them, so each equals the run on
+    its own."""
+    cfgs = [si.single_ni(2.0, 6000), si.single_ni(0.5, 20000)]
+    say("two streams, one plan")
+    plan = spx.Plan(cfgs, PARAMS)
+    ref = {s: plan.run(seed=s) for s in (1, 2)}
+    torch.cuda.synchronize()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    ba, bb = plan.allocate(), plan.allocate()
+    for _ in range(3):
+        plan.run_into(1, ba, stream=sa)
+        plan.run_into(2, bb, stream=sb)
+    torch.cuda.synchronize()
+    assert torch.equal(ba["counts"], ref[1]["counts"]) and torch.equal(ba["counters"], ref[1]["counters"].view(-1))
+    assert torch.equal(bb["counts"], ref[2]["counts"]) and torch.equal(bb["counters"], ref[2]["counters"].view(-1))
