@@ -411,10 +411,16 @@ def test_seeds_share_one_graph():
             assert torch.equal(o[key], f[key]), (seed, key)
     assert not torch.equal(outs[0][1]["counts"], outs[1][1]["counts"])
     assert torch.equal(outs[0][1]["records"], outs[4][1]["records"])
-    # a new set of outputs (no records) needs a graph of its own
-    plan.run(seed=3, records=False)
+    # without records the record pointer of the nodes is null: still the same graph
+    o = plan.run(seed=4, records=False)
+    torch.cuda.synchronize()
+    assert plan.graph_info()[0] == 1
+    assert torch.equal(o["counts"], outs[1][1]["counts"])
+    # arrival tallies run other kernel instances: a graph of their own
+    o = plan.run(seed=4, arrivals=True)
     torch.cuda.synchronize()
     assert plan.graph_info()[0] == 2
+    assert torch.equal(o["counts"], outs[1][1]["counts"])
 
 
 def test_runs_on_two_streams_are_ordered():
