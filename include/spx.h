@@ -239,6 +239,21 @@ int spx_graph_info(const spx_plan* plan, uint64_t* instantiations, uint64_t* nod
  * SPX_EINVAL for missing required outputs or a partial set of arrival outputs. */
 int spx_run_ex(spx_plan* plan, uint64_t seed, const spx_outputs* out, void* stream);
 
+/* spx_run_ex for callers that cannot allocate device memory (code under stream capture,
+ * serving loops, harnesses that forbid hipMalloc): a batched FP32 plan's run that allocates
+ * nothing.  Its kernels keep the queue of thermalised atoms and the ticket counters in a
+ * static device array of the library (64 MiB per device, held from the library's load until
+ * the process ends) instead of the plan's memory, and are enqueued on `stream` directly (no
+ * graph).  Outputs as spx_run_ex (caller-owned, overwritten), bit-identical to its results.
+ * The particles run in rounds of at most (64 MiB - 256 B) / 48 B - (queue slots the launch
+ * shape's waves may leave unused: 64 per wave) tickets, so any plan size runs, in more rounds
+ * than spx_run uses.  Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (another stream, another host thread, another plan) race and corrupt each other's
+ * results, so order them.  SPX_EINVAL for precision 64 plans, missing outputs, and a launch
+ * shape whose unused-slot slack alone exceeds the array; SPX_EDEVICE if the array's device
+ * address cannot be found.  No hipMalloc, hipFree or graph instantiation. */
+int spx_run_noalloc(spx_plan* plan, uint64_t seed, const spx_outputs* out, void* stream);
+
 /* Bin edges of the arrival tallies as the kernels use them: energy edges [61] (eV) and the
  * cosines of the angle edges [91], in double (plain FP64 path) and float (batched FP32 path;
  * the double values rounded).  Any pointer may be NULL. */

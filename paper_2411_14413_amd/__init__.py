@@ -174,6 +174,15 @@ class Plan:
         check(lib().spx_run(self._h, int(seed) & (2**64 - 1), _ptr(bufs["counts"]), _ptr(bufs["counters"]),
                             _ptr(bufs.get("profiles")), _ptr(bufs.get("records")), _stream(stream)), "spx_run")
 
+    def run_noalloc_into(self, seed: int, bufs: Dict[str, object], stream=None) -> None:
+        """As run_into, through the entry point that allocates nothing (queue and counters in
+        the library's static scratch array; calls on one GPU must not overlap)."""
+        o = N.Outputs(_ptr(bufs["counts"]), _ptr(bufs["counters"]), _ptr(bufs.get("profiles")),
+                      _ptr(bufs.get("records")), _ptr(bufs.get("arrival_energy")), _ptr(bufs.get("arrival_angle")),
+                      _ptr(bufs.get("energy_sum")))
+        check(lib().spx_run_noalloc(self._h, int(seed) & (2**64 - 1), ctypes.byref(o), _stream(stream)),
+              "spx_run_noalloc")
+
     def run(self, seed: int = 0, profiles: bool = True, records: bool = False, arrivals: bool = False,
             stream=None) -> Dict[str, object]:
         bufs = self.allocate(profiles=profiles, records=records, arrivals=arrivals)

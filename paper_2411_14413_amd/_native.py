@@ -89,6 +89,7 @@ SIGNATURES = {
     "spx_plan_layout": (ctypes.c_int, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "spx_run": (ctypes.c_int, [_vp, _u64, _vp, _vp, _vp, _vp, _vp]),
     "spx_run_ex": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(Outputs), _vp]),
+    "spx_run_noalloc": (ctypes.c_int, [_vp, _u64, ctypes.POINTER(Outputs), _vp]),
     "spx_graph_info": (ctypes.c_int, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "spx_arrival_edges": (ctypes.c_int, [ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), ctypes.POINTER(ctypes.c_float),
                                          ctypes.POINTER(ctypes.c_float)]),

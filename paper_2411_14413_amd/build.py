@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libspx.so")
-SOURCES = ["api.hip", "transport.hip", "table_build.hip", "composition.hip", "inversion.hip"]
+SOURCES = ["api.hip", "transport.hip", "table_build.hip", "composition.hip", "inversion.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

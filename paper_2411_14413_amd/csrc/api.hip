@@ -662,7 +662,7 @@ struct ListSink : LaunchSink {
     }
 };
 
-static Shape plan_shape(const Plan* P)
+Shape plan_shape(const Plan* P)
 {
     Shape sh;
     sh.blocks = P->blocks;

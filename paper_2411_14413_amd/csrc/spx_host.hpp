@@ -257,6 +257,8 @@ struct StreamSink : LaunchSink {
     int put(const KLaunch& k) override;
 };
 uint64_t rounds_of(uint64_t total, uint64_t round_max = ROUND_MAX);
+// The plan's current launch geometry and thresholds.
+Shape plan_shape(const Plan* P);
 int launch_transport64(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st);
 // Arrival bin edges in double (as the comparator uses them); the batched path rounds them to float.
 void arrival_edges(double* e_edges, double* c_edges);
