@@ -63,7 +63,10 @@ extern "C" {
 #define SPX_C_COLLISIONS 4      /* ballistic flights that ended in a gas collision */
 #define SPX_C_DIFFUSIVE 5       /* diffusive steps that ended in the gas */
 #define SPX_C_THERMALIZED 6     /* particles that reached the diffusive (thermalised) state */
-#define SPX_N_COUNTERS 7
+#define SPX_C_TESTED 7          /* diffusive steps tested against the surfaces: a work counter, not a
+                                   result (the batched FP32 walk tests only the steps that leave their
+                                   clearance balls; the plain FP64 path tests every step) */
+#define SPX_N_COUNTERS 8
 
 /* Magnetron cathode: planar circular target (Methods, "The SIMTRA Python wrapper": the
  * magnetron object holds the element, the racetrack and the geometry). */

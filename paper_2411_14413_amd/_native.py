@@ -14,8 +14,9 @@ LIB_PATH = os.path.join(HERE, "libspx.so")
 
 SPX_OK, SPX_EINVAL, SPX_ENOMEM, SPX_EDEVICE, SPX_ESTATE = 0, -1, -2, -3, -4
 DEPOSITED, WALL, ESCAPED = 1, 2, 3
-N_COUNTERS = 7
-COUNTER_NAMES = ("launched", "deposited", "wall", "escaped", "collisions", "diffusive_steps", "thermalized")
+N_COUNTERS = 8
+COUNTER_NAMES = ("launched", "deposited", "wall", "escaped", "collisions", "diffusive_steps", "thermalized",
+                 "tested_steps")
 
 d3 = ctypes.c_double * 3
 

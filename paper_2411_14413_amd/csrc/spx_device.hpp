@@ -18,7 +18,9 @@ namespace spx {
 
 enum : int { ST_DEAD = 0, ST_BALLISTIC = 1, ST_DIFFUSIVE = 2 };
 enum : int { HIT_NONE = 0, HIT_DEPOSITED = 1, HIT_WALL = 2, HIT_ESCAPED = 3 };
-enum : int { C_LAUNCHED = 0, C_DEPOSITED, C_WALL, C_ESCAPED, C_COLLISIONS, C_DIFFUSIVE, C_THERMALIZED, N_COUNTERS };
+// C_TESTED: diffusive steps tested against the surfaces (a work counter: the batched walk tests
+// only the steps that leave their clearance balls, the plain comparator every step)
+enum : int { C_LAUNCHED = 0, C_DEPOSITED, C_WALL, C_ESCAPED, C_COLLISIONS, C_DIFFUSIVE, C_THERMALIZED, C_TESTED, N_COUNTERS };
 
 // --------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11); the key words are uniform

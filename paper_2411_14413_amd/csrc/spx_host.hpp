@@ -110,7 +110,7 @@ struct Outputs {
 constexpr uint64_t ROUND_MAX = 1ull << 28;   // tickets per round: a 12.9 GB queue of thermalised atoms
 constexpr uint64_t QUEUE_CHUNK = 64;         // queue slots a wave reserves per atomic
 constexpr uint64_t QUEUE_SLACK_WAVES = 8192;  // waves that may leave slots unused (32 per CU, 256 CUs)
-constexpr size_t LDS_COUNTERS_MAX = 16384;   // bytes: up to 292 segments
+constexpr size_t LDS_COUNTERS_MAX = 16384;   // bytes: up to 256 segments
 constexpr int RT_MAX_NODES = 256;             // nodes of a measured racetrack profile
 constexpr int OBJ_MAX_SEG = 32;               // absorbing objects of one (config, cathode) run
 constexpr uint64_t TICKET_CHUNK = 64;        // queued atoms a diffusive wave claims per global atomic

@@ -53,7 +53,7 @@ __device__ __forceinline__ void write_record(spx_record* rec, const SegDev<R>& s
 // flushed to the block's LDS counters (or HBM) when the lane moves to another segment.
 struct LaneAcc {
     int seg = -1;
-    uint32_t c[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0};
+    uint32_t c[N_COUNTERS] = {};
 };
 
 struct BlockTally {
@@ -287,6 +287,7 @@ __device__ __forceinline__ void resolve_held(const TransportArgs& a, const Block
                                              Particle<float>& p, LaneAcc& acc, bool& held, uint64_t H)
 {
     const int sL = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)H) - 1);
+    acc.c[C_TESTED] += held ? 1u : 0u;
     if (__ballot(held && seg != sL) == 0) {
         if (held) {
             held = false;
@@ -509,7 +510,7 @@ __global__ void __launch_bounds__(256) k_transport64(const SegDev<double>* __res
 {
     const SegDev<double>& s = *segp;
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t acc[N_COUNTERS] = {0, 0, 0, 0, 0, 0, 0};
+    uint32_t acc[N_COUNTERS] = {};
     if (i < s.N) {
         const uint32_t pid = (uint32_t)i;
         Particle<double> p;
@@ -523,6 +524,9 @@ __global__ void __launch_bounds__(256) k_transport64(const SegDev<double>* __res
         acc[C_COLLISIONS] = p.ncoll;
         acc[C_DIFFUSIVE] = p.ndiff;
         acc[C_THERMALIZED] = (p.st == ST_DIFFUSIVE) ? 1u : 0u;
+        // every diffusive step is tested here: those that ended in the gas and the last one
+        // (unless the history stopped at the event cap)
+        acc[C_TESTED] = p.ndiff + ((p.st == ST_DIFFUSIVE && t.state != HIT_ESCAPED) ? 1u : 0u);
         if (t.state == HIT_DEPOSITED) {
             const uint64_t b = s.bin_off + (uint64_t)t.bin;
             atomicAdd(&counts[b], 1ull);

@@ -58,12 +58,14 @@ def _check_integer_identities(plan, out):
 
 
 def _sampled_parity(plan, out, cfgs, seed, per_seg, rng):
+    """per_seg: particles sampled per segment (an int, or a list with one count per segment)."""
     first = list(plan.first)
     seg_ids, pids = [], []
     for k, N in enumerate(plan.seg_particles):
         if N == 0:
             continue
-        p = rng.choice(N, size=min(per_seg, N), replace=False)
+        want = per_seg[k] if isinstance(per_seg, (list, tuple)) else per_seg
+        p = rng.choice(N, size=min(want, N), replace=False)
         seg_ids += [k] * len(p)
         pids += list(p)
     seg_ids, pids = np.array(seg_ids), np.array(pids)
@@ -126,6 +128,28 @@ def test_fullsize_quaternary_compositions():
         b = r["counts"][k].astype(np.float64)
         z = (a - b) / np.sqrt(np.maximum(a + b, 1.0))
         assert np.abs(z).max() < 3.0
+    # the hand-written backward at the fit's full size: 1024 power vectors x 342 areas x 4
+    # cathodes on these area profiles, target = the composition at the first power vector,
+    # against float64 torch autograd (the oracle) on the same float32-rounded inputs
+    ci = si.composition_inputs(batch=1024)
+    f32 = f_gpu.float()
+    fr32 = f32.mean(dim=1)
+    ins = [f32.double().cpu().numpy(), ci.a, ci.b, ci.P, ci.M, ci.rho, fr32.double().cpu().numpy()]
+    ins = [np.asarray(x, dtype=np.float32).astype(np.float64) for x in ins]
+    c_t = oracle.composition(*ins[:3], ins[3][:1], *ins[4:])[0]
+    ref = oracle.composition_grads(*ins, c_t[None])
+    dev = [torch.as_tensor(x, dtype=torch.float32, device="cuda").contiguous().requires_grad_(True) for x in ins]
+    c = spx.CompositionMap.apply(*dev)
+    loss = spx.SquaredDistance.apply(c, torch.as_tensor(c_t, dtype=torch.float32, device="cuda")).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    say(f"  backward at B=1024, J=342, K=4: loss {float(loss.detach()):.6g} (oracle {ref['loss']:.6g})")
+    assert abs(float(loss.detach()) / ref["loss"] - 1) < 1e-4
+    for name, t in zip(("f", "a", "b", "P", "M", "rho", "fref"), dev):
+        gr = t.grad.cpu().numpy().astype(np.float64)
+        err = np.abs(gr - ref[name]).max() / np.abs(ref[name]).max()
+        say(f"    grad {name}: rel err {err:.2e}")
+        assert err < 2e-4, (name, err)
 
 
 def test_fullsize_sweep():
@@ -133,9 +157,14 @@ def test_fullsize_sweep():
     say(f"full size: 64-chamber sweep, {si.total_particles(cfgs)} particles in one launch")
     plan, out = _run_full(cfgs, seed=2)
     _check_integer_identities(plan, out)
-    m, per = _sampled_parity(plan, out, cfgs, 2, 40, np.random.default_rng(2))
-    say(f"  sampled parity {m}, worst segment {per.min()}")
-    assert m["frac"] >= 0.99 and per.min() >= 0.9
+    # 200 particles of every segment, 400 of those at 1 Pa and above, where the walks are
+    # longest and the FP32 drift largest
+    press = [cfg.chamber.pressure for cfg in cfgs for _ in cfg.cathodes]
+    per_seg = [400 if p >= 1.0 else 200 for p in press]
+    m, per = _sampled_parity(plan, out, cfgs, 2, per_seg, np.random.default_rng(2))
+    hi = np.array([p >= 1.0 for p, N in zip(press, plan.seg_particles) if N > 0])
+    say(f"  sampled parity {m}, worst segment {per.min()}, worst at >= 1 Pa {per[hi].min()}")
+    assert m["frac"] >= 0.99 and per.min() >= 0.97
 
 
 def test_fullsize_two_rounds():

@@ -440,3 +440,23 @@ def test_runs_on_two_streams_are_ordered():
     torch.cuda.synchronize()
     assert torch.equal(ba["counts"], ref[1]["counts"]) and torch.equal(ba["counters"], ref[1]["counters"].view(-1))
     assert torch.equal(bb["counts"], ref[2]["counts"]) and torch.equal(bb["counters"], ref[2]["counters"].view(-1))
+
+
+def test_tested_step_counter():
+    """The work counter of diffusive steps tested against the surfaces: every step on the plain
+    FP64 path (steps ended in the gas plus the last one of each thermalised atom), and on the
+    batched path only those that left their clearance balls, the first step of each walk
+    among them."""
+    cfgs = [si.single_ni(2.0, 3000), si.quaternary(0.5, 25.0, 150.0, [3000, 800, 2000, 1200])]
+    say("tested-step counter")
+    C = {}
+    for prec in (32, 64):
+        C[prec] = spx.Plan(cfgs, PARAMS, precision=prec).run(seed=17)["counters"].cpu().numpy()
+    torch.cuda.synchronize()
+    c64, c32 = C[64], C[32]
+    assert np.all(c64[:, 3] == 0)
+    assert np.array_equal(c64[:, 7], c64[:, 5] + c64[:, 6])
+    assert np.all(c32[:, 7] >= c32[:, 6]) and np.all(c32[:, 7] <= c32[:, 5] + c32[:, 6])
+    frac = c32[:, 7].sum() / (c32[:, 5] + c32[:, 6]).sum()
+    say(f"  batched walk tests {frac:.3%} of its diffusive steps")
+    assert 0 < frac < 0.2
