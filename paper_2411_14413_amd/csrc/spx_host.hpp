@@ -59,7 +59,8 @@ struct alignas(16) ThermRec {
     uint32_t pid;               // particle index within its segment
     uint32_t seg;               // segment
     uint32_t e;                 // events taken so far
-    uint32_t pad[2];
+    uint32_t lam_bits;          // the segment's lam_th ln 2 (float bits) and Philox counter word: the
+    uint32_t cfgcat;            // two numbers of the segment a diffusive step needs
 };
 static_assert(sizeof(ThermRec) == 48, "ThermRec layout");
 

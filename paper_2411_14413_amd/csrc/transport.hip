@@ -4,7 +4,7 @@
 // at most ROUND_MAX tickets, each round as two persistent launches.  k_ballistic32 takes
 // every ticket of the round from its launch through its ballistic flights and collisions;
 // an atom that ends on a surface (or escapes) is finished there, an atom that thermalises
-// is handed over to a queue in HBM (48 B).  k_diffusive32 then runs the diffusive walks of
+// is handed over to a queue in HBM (48 B, with the two numbers of its segment a step needs).  k_diffusive32 then runs the diffusive walks of
 // the queued atoms.  Each lane holds one atom in registers; when lanes die, the wave claims
 // a run of tickets with a single atomic (ballot + mbcnt prefix gives each dead lane its
 // ticket).  Splitting the history at thermalisation keeps every lane of a wave in the same
@@ -199,8 +199,8 @@ struct QRun {
 // Lanes whose atom thermalised in the last flight hand it to the diffusive queue and become
 // free.  Slots come from the wave's run (a hand-over may continue into a fresh run).  Their
 // collisions are counted here; thermalisation itself is counted when the walk ends.
-__device__ __forceinline__ void hand_over(const TransportArgs& a, uint32_t pid, int seg, Particle<float>& p,
-                                          LaneAcc& acc, QRun& Q, int lane)
+__device__ __forceinline__ void hand_over(const TransportArgs& a, const SegDev<float>& S, uint32_t pid, int seg,
+                                          Particle<float>& p, LaneAcc& acc, QRun& Q, int lane)
 {
     const uint64_t T = __ballot(p.st == ST_DIFFUSIVE);
     if (T == 0) return;
@@ -225,7 +225,8 @@ __device__ __forceinline__ void hand_over(const TransportArgs& a, uint32_t pid, 
         r.pid = pid;
         r.seg = (uint32_t)seg;
         r.e = p.e;
-        r.pad[0] = r.pad[1] = 0u;
+        r.lam_bits = __float_as_uint(S.lam_l2);
+        r.cfgcat = S.cfgcat;
         a.queue[slot] = r;
         acc.c[C_COLLISIONS] += p.ncoll;
         p.st = ST_DEAD;
@@ -256,7 +257,7 @@ __device__ __forceinline__ void ballistic_loop(const TransportArgs& a, const Blo
             const Term t = step_mode<float, ST_BALLISTIC>(S, a.tab, a.k0, a.k1, pid, a.cap, p);
             if (t.state != HIT_NONE) terminate<ARR>(a, bt, S, pid, p, t, acc);
         }
-        hand_over(a, pid, seg, p, acc, Q, lane);
+        hand_over(a, S, pid, seg, p, acc, Q, lane);
         if (__ballot(p.st == ST_BALLISTIC) == 0) break;
         if (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_ballistic) break;
     }
@@ -397,7 +398,7 @@ k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
                 const Term t = step_mode<float, ST_BALLISTIC>(s, a.tab, a.k0, a.k1, pid, a.cap, p);
                 if (t.state != HIT_NONE) terminate<ARR>(a, bt, s, pid, p, t, acc);
             }
-            hand_over(a, pid, seg, p, acc, Q, lane);
+            hand_over(a, segs[seg], pid, seg, p, acc, Q, lane);
         }
     }
     close_run(a, Q, lane);
@@ -450,8 +451,8 @@ __device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<f
                     acc.seg = sg;
                 }
                 seg = sg;
-                lam_l2 = segs[sg].lam_l2;
-                cfgcat = segs[sg].cfgcat;
+                lam_l2 = __uint_as_float(r.lam_bits);
+                cfgcat = r.cfgcat;
             }
         }
         const uint64_t D = __ballot(p.st == ST_DIFFUSIVE);
