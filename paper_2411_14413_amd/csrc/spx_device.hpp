@@ -620,14 +620,16 @@ __device__ __forceinline__ Term step_mode(const SegDev<R>& s, const TabDev<R>& t
     }
     R t, qu = (R)0, qv = (R)0;
     const HitF h = hit_test(s, p.x, p.d, ell, t, qu, qv, e == 1u);
-    if (h.state != HIT_NONE) {
+    // one compensated move: to the surface hit, else the whole flight (a wave whose lanes
+    // differ runs the move once)
+    const bool hit = h.state != HIT_NONE, finite = ell < m_inf<R>();
+    if (hit || finite) {
+        const R mv = hit ? t : ell;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) kahan_add(p.x[i], p.xc[i], t * p.d[i]);
-        return hit_term(s, h.state, qu, qv, p.d);
+        for (int i = 0; i < 3; ++i) kahan_add(p.x[i], p.xc[i], mv * p.d[i]);
     }
-    if (!(ell < m_inf<R>())) return Term{HIT_ESCAPED, -1, 0.f};
-#pragma unroll
-    for (int i = 0; i < 3; ++i) kahan_add(p.x[i], p.xc[i], ell * p.d[i]);
+    if (hit) return hit_term(s, h.state, qu, qv, p.d);
+    if (!finite) return Term{HIT_ESCAPED, -1, 0.f};
     if (MODE == ST_BALLISTIC) {
         R V[3] = {(R)0, (R)0, (R)0};
         if (s.gas_motion) gas_velocity(s, philox4x32_10(make_uint4(pid, e, s.cfgcat, 1u), k0, k1), V);

@@ -245,21 +245,51 @@ __device__ __forceinline__ void close_run(const TransportArgs& a, const QRun& Q,
     if (Q.q + (uint64_t)lane < Q.q_end) a.queue[Q.q + lane].pid = 0xFFFFFFFFu;
 }
 
-// Ballistic flights of the lanes in segment S (uniform: its constants stay in scalar
-// registers) until the wave should refill or has no ballistic lane left.
+// A history that ended in the ballistic phase waits for the wave's next refill point, where the
+// ended histories and the thermalised atoms of the wave are settled together (a lane would idle
+// until then anyway): its outcome is packed into the clearance-radius register, unused in this
+// phase, as state | bin << 2.
+constexpr int ST_ENDED = 3;
+
+__device__ __forceinline__ void mark_ended(Particle<float>& p, const Term& t)
+{
+    p.st = ST_ENDED;
+    p.r2 = __uint_as_float((uint32_t)t.state | ((uint32_t)(t.bin < 0 ? 0 : t.bin) << 2));
+}
+
+// Settle the wave's ended histories (counters, tally, record) and queue its thermalised atoms.
+// The incidence cosine of a deposit is recomputed from its direction, with the operations of
+// hit_term.
 template <bool ARR>
-__device__ __forceinline__ void ballistic_loop(const TransportArgs& a, const BlockTally& bt, const SegDev<float>& S,
-                                               uint32_t pid, int seg, Particle<float>& p, LaneAcc& acc, QRun& Q,
-                                               bool drained, int lane)
+__device__ __forceinline__ void settle_ballistic(const TransportArgs& a, const BlockTally& bt,
+                                                 const SegDev<float>* __restrict__ segs, uint32_t pid, int seg,
+                                                 Particle<float>& p, LaneAcc& acc, QRun& Q, int lane)
+{
+    if (__ballot(p.st == ST_ENDED) != 0 && p.st == ST_ENDED) {
+        const SegDev<float>& s = segs[seg];
+        const uint32_t bits = __float_as_uint(p.r2);
+        Term t;
+        t.state = (int)(bits & 3u);
+        t.bin = t.state == HIT_DEPOSITED ? (int)(bits >> 2) : -1;
+        t.cos_in = t.state == HIT_DEPOSITED ? (float)(-dot3(p.d, s.sub_n)) : 0.f;
+        terminate<ARR>(a, bt, s, pid, p, t, acc);
+    }
+    if (__ballot(p.st == ST_DIFFUSIVE) != 0) hand_over(a, segs[seg], pid, seg, p, acc, Q, lane);
+}
+
+// Ballistic flights of the lanes in segment S (uniform: its constants stay in scalar
+// registers) until the wave should refill (lanes that ended, thermalised or are free count) or
+// has no ballistic lane left.
+__device__ __forceinline__ void ballistic_loop(const TransportArgs& a, const SegDev<float>& S, uint32_t pid,
+                                               Particle<float>& p, bool drained)
 {
     for (;;) {
         if (p.st == ST_BALLISTIC) {
             const Term t = step_mode<float, ST_BALLISTIC>(S, a.tab, a.k0, a.k1, pid, a.cap, p);
-            if (t.state != HIT_NONE) terminate<ARR>(a, bt, S, pid, p, t, acc);
+            if (t.state != HIT_NONE) mark_ended(p, t);
         }
-        hand_over(a, S, pid, seg, p, acc, Q, lane);
         if (__ballot(p.st == ST_BALLISTIC) == 0) break;
-        if (!drained && __popcll(__ballot(p.st == ST_DEAD)) >= a.refill_ballistic) break;
+        if (!drained && __popcll(__ballot(p.st != ST_BALLISTIC)) >= a.refill_ballistic) break;
     }
 }
 
@@ -360,18 +390,28 @@ k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
     LaneAcc acc;
     Tickets T;
     QRun Q;
+    int cur_pos = 0, last_pos = 0;        // wave-uniform current position in ticket order ...
+    uint64_t cur_lo = 0, cur_hi = 0;      // ... and its ticket range (empty until the first refill)
     for (;;) {
+        settle_ballistic<ARR>(a, bt, segs, pid, seg, p, acc, Q, lane);
         const uint64_t dead = __ballot(p.st == ST_DEAD);
         const int n_dead = __popcll(dead);
         if (!T.drained && n_dead > 0 && (n_dead >= a.refill_ballistic || n_dead == 64)) {
             const uint64_t my = claim(T, &a.qstate[0], a.chunk_ballistic, a.total, dead, lane);
             if (my != ~0ull) {
                 const uint64_t g = a.tbase + my;
-                int lo = 0, hi = a.n_seg;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (a.tfirst[mid] <= g) lo = mid; else hi = mid;
+                // the ticket's position in ticket order: the wave's current one (tickets of a
+                // run are consecutive, segments long), else a binary search of the prefix table
+                int lo = cur_pos;
+                if (!(g >= cur_lo && g < cur_hi)) {
+                    lo = 0;
+                    int hi = a.n_seg;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (a.tfirst[mid] <= g) lo = mid; else hi = mid;
+                    }
                 }
+                last_pos = lo;
                 const int sg = (int)a.torder[lo];
                 pid = (uint32_t)(g - a.tfirst[lo]);
                 if (sg != acc.seg) {
@@ -382,6 +422,13 @@ k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
                 start(segs[seg], a.k0, a.k1, pid, p);
                 acc.c[C_LAUNCHED] += 1;
             }
+            // the position of the wave's last new ticket becomes the current one
+            const uint64_t got = __ballot(my != ~0ull);
+            if (got != 0) {
+                cur_pos = __builtin_amdgcn_readlane(last_pos, 63 - __clzll((long long)got));
+                cur_lo = a.tfirst[cur_pos];
+                cur_hi = a.tfirst[cur_pos + 1];
+            }
         }
         const uint64_t B = __ballot(p.st == ST_BALLISTIC);
         if (B == 0) {
@@ -390,15 +437,12 @@ k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
         }
         const int s0 = __builtin_amdgcn_readlane(seg, __ffsll((unsigned long long)B) - 1);
         if (__ballot(p.st == ST_BALLISTIC && seg != s0) == 0) {
-            ballistic_loop<ARR>(a, bt, segs[s0], pid, s0, p, acc, Q, T.drained, lane);
-        } else {
+            ballistic_loop(a, segs[s0], pid, p, T.drained);
+        } else if (p.st == ST_BALLISTIC) {
             // lanes of several segments: one flight with per-lane constants
-            if (p.st == ST_BALLISTIC) {
-                const SegDev<float>& s = segs[seg];
-                const Term t = step_mode<float, ST_BALLISTIC>(s, a.tab, a.k0, a.k1, pid, a.cap, p);
-                if (t.state != HIT_NONE) terminate<ARR>(a, bt, s, pid, p, t, acc);
-            }
-            hand_over(a, segs[seg], pid, seg, p, acc, Q, lane);
+            const SegDev<float>& s = segs[seg];
+            const Term t = step_mode<float, ST_BALLISTIC>(s, a.tab, a.k0, a.k1, pid, a.cap, p);
+            if (t.state != HIT_NONE) mark_ended(p, t);
         }
     }
     close_run(a, Q, lane);
