@@ -57,6 +57,7 @@ OBJ_CLEAR = {"disc": 25, "rect": 22, "tube": 23}
 # Peak: the FP32 vector rate of the MI355X, 157.3 TFLOP/s = 78.6e12 FMA/s, i.e. 128 lanes per
 # CU per clock (256 CUs, 2.4 GHz); one slot = one full-rate 32-bit lane operation.
 PEAK_ALU = 256 * 128 * 2.4e9
+QUEUE_RECORD_BYTES = 48   # one thermalised atom handed from the ballistic to the diffusive phase
 
 
 def segment_objects(cfgs):
@@ -84,16 +85,20 @@ def algorithmic_ops(counters, cfgs):
     return ops_b, ops_d
 
 
+# the sources the two transport kernels are compiled from (their device code, launch
+# arguments and queue record layout)
+TRANSPORT_SOURCES = ("spx_device.hpp", "spx_host.hpp", "transport.hip")
+
+
 def kernel_source_hash():
-    """Digest of the HIP sources: HBM traffic taken with rocprofv3 counters is reported only
-    for the kernels it was measured on."""
+    """Digest of the transport kernels' sources: HBM traffic taken with rocprofv3 counters is
+    reported only for the kernels it was measured on."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2411_14413_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            h.update(name.encode())
-            h.update(open(os.path.join(csrc, name), "rb").read())
+    for name in TRANSPORT_SOURCES:
+        h.update(name.encode())
+        h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -295,16 +300,21 @@ def run_workload(name, args, params, n_steps, n_warmup, with_phases=True):
     ms_b = float(np.mean([p[0] for p in phases]))
     ms_d = float(np.mean([p[1] for p in phases]))
     kern = {"k_ballistic32": (ops_b, ms_b), "k_diffusive32": (ops_d, ms_d)}
-    coll, diff, tested = (float(counters[:, i].sum()) for i in (4, 5, 7))
+    coll, diff, therm, tested = (float(counters[:, i].sum()) for i in (4, 5, 6, 7))
     rep = {"workload": desc, "particles_per_step": int(n_part), "segments": plan.n_segments, "launch": launch,
            "ms_per_step": ms_step, "particles_per_s": n_part / (ms_step * 1e-3),
            "collisions_per_s": (coll + diff) / (ms_step * 1e-3),
            "ballistic_collisions_per_s": coll / (ms_step * 1e-3), "diffusive_steps_per_s": diff / (ms_step * 1e-3),
-           "tested_step_fraction": tested / max(diff + float(counters[:, 6].sum()), 1.0),
+           "tested_step_fraction": tested / max(diff + therm, 1.0),
+           # each thermalised atom is one 48-byte queue record, written by the ballistic kernel
+           # and read by the diffusive one: the bulk of either kernel's algorithmic HBM bytes
+           "thermalized_per_step": int(therm), "queue_bytes_per_launch": int(QUEUE_RECORD_BYTES * therm),
            "step_ms_events": {"median": float(np.median(ms)), "min": float(min(ms)), "max": float(max(ms))},
            "setup_s": {"plan_and_table": setup_s, "autotune": tune_s},
            "kernels": {k: {"ops": o, "ms": t, "achieved_TOPs": o / (t * 1e-3) / 1e12 if t > 0 else None,
-                           "frac": o / (t * 1e-3) / PEAK_ALU if t > 0 else None} for k, (o, t) in kern.items()}}
+                           "frac": o / (t * 1e-3) / PEAK_ALU if t > 0 else None,
+                           "traffic": None if args.arrivals else measured_traffic(k, name)}
+                       for k, (o, t) in kern.items()}}
     return plan, cfgs, bufs, counters, kern, rep
 
 
@@ -366,12 +376,15 @@ def main():
                     traffic=None if args.arrivals else measured_traffic(dominant, args.workload),
                     ops_per_launch=ops, launch_ms=ms_k,
                     phases={k: dict(ops=o, ms=t, achieved=o / (t * 1e-3) / 1e12 if t > 0 else None,
-                                    frac=o / (t * 1e-3) / PEAK_ALU if t > 0 else None) for k, (o, t) in kern.items()},
+                                    frac=o / (t * 1e-3) / PEAK_ALU if t > 0 else None,
+                                    traffic=None if args.arrivals else measured_traffic(k, args.workload))
+                            for k, (o, t) in kern.items()},
                     note="VALU issue slots per lane counted from the algorithm (a 32x32->64 multiply or a native "
                          "transcendental = 4 slots; surface tests and absorbing objects charged to the flights and "
                          "to the diffusive steps the kernels report as tested); peak = 256 CU x 128 lanes x 2.4 GHz "
                          "(the FP32 vector rate); kernel time = mean over the timed steps of HIP events recorded "
-                         "between the kernels; traffic = rocprofv3 HBM bytes per launch when taken on these sources")
+                         "between the kernels; traffic = rocprofv3 HBM bytes per launch when taken on these sources, "
+                         "against queue_bytes_per_launch, the algorithmic bytes of either phase")
 
     result = {
         "metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
@@ -384,6 +397,8 @@ def main():
         "ballistic_collisions_per_s": rep["ballistic_collisions_per_s"],
         "diffusive_steps_per_s": rep["diffusive_steps_per_s"],
         "tested_step_fraction": rep["tested_step_fraction"],
+        "thermalized_per_step": rep["thermalized_per_step"],
+        "queue_bytes_per_launch": rep["queue_bytes_per_launch"],
         "step_ms_events": rep["step_ms_events"],
         "setup_s": rep["setup_s"],
         "roofline": roofline,

@@ -262,9 +262,11 @@ int spx_run_noalloc(spx_plan* plan, uint64_t seed, const spx_outputs* out, void*
  * the double values rounded).  Any pointer may be NULL. */
 int spx_arrival_edges(double* h_energy_edges, double* h_cos_edges, float* h_energy_edges32, float* h_cos_edges32);
 
-/* Choose launch parameters of the FP32 transport (block size, the two refill thresholds, then
- * the deferral threshold) by timing short runs on `stream`; synchronous; results are
- * unaffected. */
+/* Choose launch parameters of the FP32 transport by timing short runs on `stream` (a sample
+ * with the plan's mix, its outputs in scratch memory the call allocates and frees): per block
+ * size, the ballistic refill threshold by the ballistic kernel's time and the diffusive one by
+ * the diffusive kernel's, then the deferral threshold by the diffusive kernel's time.
+ * Synchronous; not allowed inside a stream capture (SPX_ESTATE); results are unaffected. */
 int spx_autotune(spx_plan* plan, void* stream);
 
 /* Current FP32-transport launch parameters of its two persistent kernels (the ballistic

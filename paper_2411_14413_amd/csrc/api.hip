@@ -825,19 +825,27 @@ static int autotune(Plan* P, hipStream_t st)
         const uint64_t Nk = P->seg[order[o]].N;
         tf[o + 1] = tf[o] + std::min<uint64_t>(Nk, (uint64_t)std::ceil(frac * (double)Nk));
     }
+    if (tf[n] == 0) return SPX_OK;     // no particles: nothing to time, the defaults stay
     uint64_t *d_tf = nullptr, *d_counts = nullptr, *d_ctr = nullptr;
     SPX_TRY(dalloc(&d_tf, n + 1));
     int rc = dalloc(&d_counts, P->n_bins_total);
     if (rc == SPX_OK) rc = dalloc(&d_ctr, (size_t)n * N_COUNTERS);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (rc == SPX_OK && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) rc = SPX_EDEVICE;
+    // events around the two phases of every round of the sample
+    std::vector<hipEvent_t> ev(3 * rounds_of(tf[n]), nullptr);
+    for (auto& e : ev)
+        if (rc == SPX_OK && hipEventCreate(&e) != hipSuccess) rc = SPX_EDEVICE;
     if (rc == SPX_OK && hipMemcpyAsync(d_tf, tf.data(), sizeof(uint64_t) * (n + 1), hipMemcpyHostToDevice, st) != hipSuccess)
         rc = SPX_EDEVICE;
-    // best of two timed runs of one launch shape on the sample
-    auto time_shape = [&](int blocks, int blocks_d, int t, int rmin, int rbal, int defer) -> float {
-        float ms_min = 1e30f;
+    // One launch shape on the sample, best of two runs for each phase on its own: the ballistic
+    // kernel's time depends on the ballistic refill threshold, the diffusive kernel's on the
+    // diffusive refill and deferral thresholds, so each threshold is chosen by the time of its
+    // own kernel and not by a step total in which the other kernel's noise can hide it.
+    struct PhaseMs {
+        float b = 1e30f, d = 1e30f;
+    };
+    auto time_shape = [&](int blocks, int blocks_d, int t, int rmin, int rbal, int defer) -> PhaseMs {
+        PhaseMs best;
         for (int rep = 0; rep < 2 && rc == SPX_OK; ++rep) {
-            if (hipEventRecord(e0, st) != hipSuccess) rc = SPX_EDEVICE;
             Outputs to;
             to.counts = d_counts;
             to.counters = d_ctr;
@@ -852,47 +860,71 @@ static int autotune(Plan* P, hipStream_t st)
             q.queue = P->d_queue;
             q.cap = P->queue_cap;
             q.qstate = P->d_qstate;
-            StreamSink ss(st, nullptr);
+            StreamSink ss(st, ev.data());
             if (rc == SPX_OK) rc = build_transport32(P, 0x5eed, to, d_tf, tf[n], sh, q, ss);
-            if (rc == SPX_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
-                rc = SPX_EDEVICE;
-            float ms = 0.f;
-            if (rc == SPX_OK && hipEventElapsedTime(&ms, e0, e1) == hipSuccess) ms_min = std::min(ms_min, ms);
+            if (rc == SPX_OK && hipEventSynchronize(ev.back()) != hipSuccess) rc = SPX_EDEVICE;
+            float b = 0.f, d = 0.f;
+            for (size_t r = 0; r + 2 < ev.size() && rc == SPX_OK; r += 3) {
+                float t1 = 0.f, t2 = 0.f;
+                if (hipEventElapsedTime(&t1, ev[r], ev[r + 1]) != hipSuccess ||
+                    hipEventElapsedTime(&t2, ev[r + 1], ev[r + 2]) != hipSuccess)
+                    rc = SPX_EDEVICE;
+                b += t1;
+                d += t2;
+            }
+            if (rc == SPX_OK) {
+                best.b = std::min(best.b, b);
+                best.d = std::min(best.d, d);
+            }
         }
-        return ms_min;
+        return best;
     };
-    float best = 1e30f;
+    float best = 1e30f, best_d = 1e30f;
     int bb = P->blocks, bd = P->blocks_diff, bt = P->threads, br = P->refill_min, bm = P->refill_ballistic;
     int bdef = DEFER_MIN;
     const int thread_opts[] = {256, 512, 1024};
-    const int mode_opts[][2] = {{4, 4}, {4, 16}, {8, 8}};   // (refill_min, refill_ballistic)
+    // (refill_min, refill_ballistic): three runs measure three values of each threshold
+    const int mode_opts[][2] = {{4, 16}, {8, 8}, {16, 4}};
     for (int t : thread_opts) {
         if (rc != SPX_OK) break;
         int bpc = 0, bpc_d = 0;
         if (occupancy_transport32(P, t, &bpc, &bpc_d) != SPX_OK || bpc < 1 || bpc_d < 1) continue;
+        const int blocks = bpc * P->n_cu, blocks_d = std::min(blocks, bpc_d * P->n_cu);
+        PhaseMs tb;
+        int rmin = mode_opts[0][0], rbal = mode_opts[0][1];
         for (const auto& ro : mode_opts) {
-            const int blocks = bpc * P->n_cu, blocks_d = std::min(blocks, bpc_d * P->n_cu);
-            const float ms = time_shape(blocks, blocks_d, t, ro[0], ro[1], DEFER_MIN);
-            if (rc == SPX_OK && ms < best) {
-                best = ms;
-                bb = blocks;
-                bd = blocks_d;
-                bt = t;
-                br = ro[0];
-                bm = ro[1];
+            const PhaseMs ms = time_shape(blocks, blocks_d, t, ro[0], ro[1], DEFER_MIN);
+            if (rc != SPX_OK) break;
+            if (ms.b < tb.b) {
+                tb.b = ms.b;
+                rbal = ro[1];
+            }
+            if (ms.d < tb.d) {
+                tb.d = ms.d;
+                rmin = ro[0];
             }
         }
+        if (rc == SPX_OK && tb.b + tb.d < best) {
+            best = tb.b + tb.d;
+            best_d = tb.d;
+            bb = blocks;
+            bd = blocks_d;
+            bt = t;
+            br = rmin;
+            bm = rbal;
+        }
     }
-    // then the deferral threshold for that shape: more held steps per test pass pays off where
-    // steps leave their clearance balls often (near surfaces, absorbing objects)
+    // then the deferral threshold for that shape, by the diffusive kernel's time: more held
+    // steps per test pass pays off where steps leave their clearance balls often (near
+    // surfaces, absorbing objects)
     for (int defer = 2 * DEFER_MIN; defer <= 4 * DEFER_MIN && rc == SPX_OK; defer *= 2) {
-        const float ms = time_shape(bb, bd, bt, br, bm, defer);
-        if (rc != SPX_OK || !(ms < best)) break;     // doubling again only while it helps
-        best = ms;
+        const PhaseMs ms = time_shape(bb, bd, bt, br, bm, defer);
+        if (rc != SPX_OK || !(ms.d < best_d)) break;     // doubling again only while it helps
+        best_d = ms.d;
         bdef = defer;
     }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
     (void)hipFree(d_tf);
     if (d_counts) (void)hipFree(d_counts);
     if (d_ctr) (void)hipFree(d_ctr);
