@@ -248,7 +248,7 @@ int spx_run_ex(spx_plan* plan, uint64_t seed, const spx_outputs* out, void* stre
  * static device array of the library (64 MiB per device, held from the library's load until
  * the process ends) instead of the plan's memory, and are enqueued on `stream` directly (no
  * graph).  Outputs as spx_run_ex (caller-owned, overwritten), bit-identical to its results.
- * The particles run in rounds of at most (64 MiB - 256 B) / 48 B - (queue slots the launch
+ * The particles run in rounds of at most (64 MiB - 1 KiB) / 48 B - (queue slots the launch
  * shape's waves may leave unused: 64 per wave) tickets, so any plan size runs, in more rounds
  * than spx_run uses.  Every call on one GPU shares that GPU's array: calls that overlap on one
  * GPU (another stream, another host thread, another plan) race and corrupt each other's

@@ -458,7 +458,7 @@ static int create(const spx_config* cfgs, int n_cfgs, const spx_params* prm, Pla
     chk(dalloc(&P->d_theta64, (size_t)ne * ns)) && chk(dalloc(&P->d_betamax64, ne)) &&
         chk(dalloc(&P->d_theta32, (size_t)ne * ns)) && chk(dalloc(&P->d_betamax32, ne)) &&
         chk(dalloc(&P->d_seg32, n)) && chk(dalloc(&P->d_seg64, n)) && chk(dalloc(&P->d_tfirst, n + 1)) &&
-        chk(dalloc(&P->d_torder, n)) && chk(dalloc(&P->d_qstate, 3)) && chk(dalloc(&P->d_bin_off, n + 1)) &&
+        chk(dalloc(&P->d_torder, n)) && chk(dalloc(&P->d_qstate, QSTATE_WORDS)) && chk(dalloc(&P->d_bin_off, n + 1)) &&
         chk(dalloc(&P->d_seg_norm, n));
     if (rc == SPX_OK) rc = build_tables(P);
     if (rc != SPX_OK) {

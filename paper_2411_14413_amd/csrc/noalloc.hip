@@ -18,9 +18,10 @@
 namespace spx {
 
 // 64 MiB per device, held from the library's load until the process ends: the ticket
-// counters (first 256 B), then the queue (48 B per slot, 1 398 096 slots).
+// counters (first 1 KiB), then the queue (48 B per slot, 1 398 080 slots).
 constexpr size_t SCRATCH_BYTES = (size_t)64 << 20;
-constexpr size_t SCRATCH_HEAD = 256;
+constexpr size_t SCRATCH_HEAD = 1024;   // the round's counters (QSTATE_WORDS words), then the queue
+static_assert(SCRATCH_HEAD >= QSTATE_WORDS * sizeof(uint64_t), "scratch head holds the round's counters");
 static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
 
 namespace {

@@ -73,7 +73,8 @@ struct TransportArgs {
     const uint64_t* tfirst;     // [n_seg + 1] first ticket of each position in ticket order
     const uint32_t* torder;     // [n_seg] segment at each position
     ThermRec* queue;            // thermalised atoms of the round (capacity >= tickets of a round)
-    uint64_t* qstate;           // [0] ballistic ticket counter, [1] queue length, [2] diffusive ticket counter
+    uint64_t* qstate;           // [QS_TICKETS] ballistic ticket counter, [QS_QUEUE] queue length,
+                                // [QS_DIFFUSIVE] diffusive ticket counter
     unsigned long long* counts;
     unsigned long long* counters;
     spx_record* records;
@@ -110,6 +111,10 @@ struct Outputs {
 
 constexpr uint64_t ROUND_MAX = 1ull << 28;   // tickets per round: a 12.9 GB queue of thermalised atoms
 constexpr uint64_t QUEUE_CHUNK = 64;         // queue slots a wave reserves per atomic
+// The round's three counters (ballistic tickets, queue length, diffusive tickets) sit 256 bytes
+// apart: every wave's claims and queue reservations are atomics on them, and on one cache line
+// the two kinds of atomics of the ballistic phase would queue behind each other.
+constexpr uint64_t QS_TICKETS = 0, QS_QUEUE = 32, QS_DIFFUSIVE = 64, QSTATE_WORDS = 96;
 constexpr uint64_t QUEUE_SLACK_WAVES = 8192;  // waves that may leave slots unused (32 per CU, 256 CUs)
 constexpr size_t LDS_COUNTERS_MAX = 16384;   // bytes: up to 256 segments
 constexpr int RT_MAX_NODES = 256;             // nodes of a measured racetrack profile
@@ -184,7 +189,7 @@ struct Shape {
 struct QueueMem {
     ThermRec* queue = nullptr;
     uint64_t cap = 0;            // slots
-    uint64_t* qstate = nullptr;  // 3 counters
+    uint64_t* qstate = nullptr;  // QSTATE_WORDS words: the round's counters
     uint64_t round_max = ROUND_MAX;
 };
 

@@ -209,7 +209,7 @@ __device__ __forceinline__ void hand_over(const TransportArgs& a, const SegDev<f
     uint64_t fresh = 0;
     if (rem < n) {
         unsigned long long b = 0;
-        if (lane == 0) b = atomicAdd((unsigned long long*)&a.qstate[1], (unsigned long long)QUEUE_CHUNK);
+        if (lane == 0) b = atomicAdd((unsigned long long*)&a.qstate[QS_QUEUE], (unsigned long long)QUEUE_CHUNK);
         fresh = __shfl(b, 0);
     }
     if (p.st == ST_DIFFUSIVE) {
@@ -397,7 +397,7 @@ k_ballistic32(TransportArgs a, const SegDev<float>* __restrict__ segs)
         const uint64_t dead = __ballot(p.st == ST_DEAD);
         const int n_dead = __popcll(dead);
         if (!T.drained && n_dead > 0 && (n_dead >= a.refill_ballistic || n_dead == 64)) {
-            const uint64_t my = claim(T, &a.qstate[0], a.chunk_ballistic, a.total, dead, lane);
+            const uint64_t my = claim(T, &a.qstate[QS_TICKETS], a.chunk_ballistic, a.total, dead, lane);
             if (my != ~0ull) {
                 const uint64_t g = a.tbase + my;
                 // the ticket's position in ticket order: the wave's current one (tickets of a
@@ -458,7 +458,7 @@ __device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<f
     extern __shared__ unsigned long long lds[];
     BlockTally bt;
     lds_setup(a, bt, lds);
-    const uint64_t total = a.qstate[1];      // written by the ballistic phase of this round
+    const uint64_t total = a.qstate[QS_QUEUE];   // written by the ballistic phase of this round
     const int lane = threadIdx.x & 63;
     Particle<float> p;
     p.st = ST_DEAD;
@@ -473,7 +473,7 @@ __device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<f
         const uint64_t dead = __ballot(p.st == ST_DEAD);
         const int n_dead = __popcll(dead);
         if (!T.drained && n_dead > 0 && (n_dead >= a.refill_min || n_dead == 64)) {
-            const uint64_t my = claim(T, &a.qstate[2], TICKET_CHUNK, total, dead, lane);
+            const uint64_t my = claim(T, &a.qstate[QS_DIFFUSIVE], TICKET_CHUNK, total, dead, lane);
             const uint32_t qpid = my != ~0ull ? a.queue[my].pid : 0xFFFFFFFFu;
             if (qpid != 0xFFFFFFFFu) {                 // empty slots (left unused by a wave) are skipped
                 const ThermRec r = a.queue[my];
@@ -604,7 +604,7 @@ __global__ void k_zero(unsigned long long* counts, uint64_t n_counts, unsigned l
 // Reset a round's ticket counters and queue length.
 __global__ void k_round_reset(uint64_t* qstate)
 {
-    if (threadIdx.x < 3) qstate[threadIdx.x] = 0;
+    for (uint32_t i = threadIdx.x; i < QSTATE_WORDS; i += blockDim.x) qstate[i] = 0;
 }
 
 // profiles = counts / (N_seg * bin area); FP64.
