@@ -113,8 +113,6 @@ __device__ __forceinline__ float m_rcp(float x) { return __builtin_amdgcn_rcpf(x
 __device__ __forceinline__ double m_rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float m_div(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double m_div(double a, double b) { return a / b; }
-__device__ __forceinline__ float m_erf(float x) { return erff(x); }
-__device__ __forceinline__ double m_erf(double x) { return erf(x); }
 __device__ __forceinline__ float m_ninv(float p) { return normcdfinvf(p); }
 __device__ __forceinline__ double m_ninv(double p) { return normcdfinv(p); }
 __device__ __forceinline__ float m_floor(float x) { return floorf(x); }
@@ -324,6 +322,21 @@ __device__ __forceinline__ void launch(const SegDev<R>& s, uint4 r0, uint4 r1, R
     for (int i = 0; i < 3; ++i) d[i] = mu * s.cat_n[i] + st * (cf * s.cat_u[i] + sf * s.cat_v[i]);
 }
 
+// erf(x) for x >= 0, given e = exp(-x^2).  FP32: the rational approximation of Abramowitz and
+// Stegun (Handbook of Mathematical Functions, 7.1.26), erf x = 1 - t (a1 + t (a2 + ... a5 t)) e
+// with t = 1 / (1 + p x), absolute error below 1.5e-7 (a few FP32 ulp near 1), which reuses the
+// exponential the mean relative speed needs anyway.  FP64: the library erf.
+__device__ __forceinline__ float erf_given_exp(float x, float e)
+{
+    const float t = __builtin_amdgcn_rcpf(__builtin_fmaf(0.3275911f, x, 1.f));
+    float q = __builtin_fmaf(t, 1.061405429f, -1.453152027f);
+    q = __builtin_fmaf(t, q, 1.421413741f);
+    q = __builtin_fmaf(t, q, -0.284496736f);
+    q = __builtin_fmaf(t, q, 0.254829592f);
+    return __builtin_fmaf(-(t * q), e, 1.f);
+}
+__device__ __forceinline__ double erf_given_exp(double x, double) { return erf(x); }
+
 // Mean free path at energy E.
 template <typename R>
 __device__ __forceinline__ R lambda_m(const SegDev<R>& s, const TabDev<R>& tb, R E)
@@ -334,7 +347,8 @@ __device__ __forceinline__ R lambda_m(const SegDev<R>& s, const TabDev<R>& tb, R
     // moving gas: the collision rate uses the Maxwellian mean relative speed <g>(v)
     const R v = m_sqrt(E * s.two_over_Ms);
     const R xx = v * s.inv_vg;
-    const R g = s.vg * ((xx + m_div((R)0.5, xx)) * m_erf(xx) + m_exp(-xx * xx) * (R)0.56418958354775628695);
+    const R ex = m_exp(-xx * xx);
+    const R g = s.vg * ((xx + m_div((R)0.5, xx)) * erf_given_exp(xx, ex) + ex * (R)0.56418958354775628695);
     return m_div(v, nsig * g);
 }
 
