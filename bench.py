@@ -201,26 +201,27 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(cfgs, params, target_s, one_thread_s):
-    """The FP64 oracle on this host: the first n particles of every (config, cathode) on all
-    threads (n sized by a pilot to ~target_s), and a smaller sample on one thread.  Returns the
-    report and the all-threads run's records (for the accuracy of the GPU run)."""
+def cpu_baseline(cfgs, params, seed, target_s, one_thread_s):
+    """The FP64 oracle on this host with the benchmark's seed: the first n particles of every
+    (config, cathode) on all threads (n sized by a pilot to ~target_s), and a smaller sample on
+    one thread.  Returns the report and the all-threads run's records (for the accuracy of the
+    GPU run, which must use the same seed)."""
     import oracle
     oracle.table(params)                      # table build is set-up, not timed
     n0 = 500
     t = time.perf_counter()
-    oracle.run(cfgs, params, seed=0, pid_begin=0, pid_end=n0)
+    oracle.run(cfgs, params, seed=seed, pid_begin=0, pid_end=n0)
     t0 = time.perf_counter() - t
     n = int(min(max(n0, n0 * target_s / max(t0, 1e-3)), 10_000_000))
     t = time.perf_counter()
-    r = oracle.run(cfgs, params, seed=0, pid_begin=0, pid_end=n, records=True)
+    r = oracle.run(cfgs, params, seed=seed, pid_begin=0, pid_end=n, records=True)
     dt = time.perf_counter() - t
     launched = int(r["counters"][:, 0].sum())
     rate = launched / dt
     # one thread: a sample of ~one_thread_s from the all-threads rate
     n1 = int(max(50, n * one_thread_s / max(dt * r["threads"], 1e-3)))
     t = time.perf_counter()
-    r1 = oracle.run(cfgs, params, seed=0, pid_begin=0, pid_end=n1, n_threads=1)
+    r1 = oracle.run(cfgs, params, seed=seed, pid_begin=0, pid_end=n1, n_threads=1)
     dt1 = time.perf_counter() - t
     l1 = int(r1["counters"][:, 0].sum())
     rep = dict(value=rate, unit="particles/s", cores=int(r["threads"]), kind="oracle",
@@ -424,7 +425,7 @@ def main():
 
     if not args.no_cpu:
         cfgs_cpu, _ = workload(args.workload)
-        cb, ref, n_first = cpu_baseline(cfgs_cpu, params, args.cpu_seconds, args.cpu_one_thread_seconds)
+        cb, ref, n_first = cpu_baseline(cfgs_cpu, params, args.seed, args.cpu_seconds, args.cpu_one_thread_seconds)
         result["cpu_baseline"] = cb
         result["accuracy"] = accuracy(plan, cfgs, args.seed, ref, n_first,
                                       dict(profiles=False, arrivals=bool(args.arrivals)))
