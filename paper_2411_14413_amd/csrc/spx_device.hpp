@@ -289,15 +289,14 @@ __device__ __forceinline__ void launch(const SegDev<R>& s, uint4 r0, uint4 r1, R
         rr = racetrack_radius(s, u0);
     } else {
         // racetrack radius: inverse CDF of the truncated normal; the upper half takes the
-        // complement so that no precision is lost near 1
-        R z;
+        // complement so that no precision is lost near 1.  One inverse-normal call on the
+        // chosen argument (lanes of a wave fall on both sides; two calls in the two arms of a
+        // branch would each run for the whole wave).
         const R P = s.PhiA + u0 * s.dPhi;
-        if (P <= (R)0.5) {
-            z = m_ninv(P);
-        } else {
-            const R Q = s.QB + ((R)1 - u0) * s.dPhi;
-            z = -m_ninv(Q);
-        }
+        const bool lower = P <= (R)0.5;
+        const R Q = s.QB + ((R)1 - u0) * s.dPhi;
+        const R zz = m_ninv(lower ? P : Q);
+        const R z = lower ? zz : -zz;
         rr = s.rt_mu + s.rt_sig * z;
     }
     R sp, cp;
