@@ -336,7 +336,7 @@ def run(cfgs, params, seed: int, pid_begin: int = 0, pid_end: int = None, n_thre
 
     Returns ``counts`` (list of [nv, nu] uint64 arrays, one per segment),
     ``counters`` ([n_seg, 7] uint64, order COUNTER_NAMES), ``records``
-    ([n, 8] float64: x, y, z, state, bin, events, diffusive steps, final E) and
+    ([n, REC] float64: x, y, z, state, bin, events, diffusive steps, final E, incidence cosine) and
     ``threads`` (OpenMP threads used)."""
     S, prm, th, bm = _args(cfgs, params)
     n_seg = S.shape[0]
@@ -359,7 +359,7 @@ def run(cfgs, params, seed: int, pid_begin: int = 0, pid_end: int = None, n_thre
 
 
 def run_list(cfgs, params, seed: int, seg_ids, pids, n_threads: int = 0) -> np.ndarray:
-    """Records ([n, 8]) of an explicit list of (segment, particle index) pairs."""
+    """Records ([n, REC]) of an explicit list of (segment, particle index) pairs."""
     S, prm, th, bm = _args(cfgs, params)
     sid = np.ascontiguousarray(np.asarray(seg_ids, dtype=np.uint32))
     pid = np.ascontiguousarray(np.asarray(pids, dtype=np.uint32))
