@@ -26,8 +26,10 @@
  *   thermalised atoms and its ticket counters, so each spx_run / spx_run_ex and
  *   spx_autotune first makes its stream wait for the plan's previous run (an event
  *   recorded after every run); runs on different streams are therefore executed one
- *   after the other.  Inside a stream capture that wait and that record are left
- *   out, and the capturing caller orders the runs of a plan itself.
+ *   after the other.  Inside a stream capture spx_run / spx_run_ex enqueue their
+ *   kernels directly on the capturing stream (they become nodes of the caller's graph;
+ *   the plan's own graph is not used), the wait and the record are left out, and the
+ *   capturing caller orders the runs of a plan itself: they share its queue.
  *
  * Random numbers: Philox4x32-10, counter (particle, event, (config << 8) | cathode,
  * sub-block), key (seed low word, seed high word); a 32-bit word x gives

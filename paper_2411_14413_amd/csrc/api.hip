@@ -751,6 +751,17 @@ static int run(Plan* P, uint64_t seed, const Outputs& o, hipStream_t st)
     if (P->done_recorded && !capturing) SPX_HIP(hipStreamWaitEvent(st, P->done_event, 0));
     if (P->params.precision == 64) {
         SPX_TRY(launch_transport64(P, seed, o, st));
+    } else if (capturing) {
+        // inside a stream capture the kernels go straight onto the capturing stream, so that
+        // they become nodes of the caller's graph (a launch of the plan's own graph would not be
+        // recorded); the runs of the plan in that graph share its queue and are ordered by the
+        // caller
+        QueueMem q;
+        q.queue = P->d_queue;
+        q.cap = P->queue_cap;
+        q.qstate = P->d_qstate;
+        StreamSink ss(st, nullptr);
+        SPX_TRY(build_transport32(P, seed, o, P->d_tfirst, P->n_tickets, plan_shape(P), q, ss));
     } else {
         QueueMem q;
         q.queue = P->d_queue;

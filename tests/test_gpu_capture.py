@@ -1,0 +1,89 @@
+"""spx_run_noalloc under stream capture: the entry point that allocates nothing is recorded into
+a graph (torch.cuda.CUDAGraph around the library call on the capturing stream) and the graph is
+replayed several times, with eager runs of the same plan, fills of the outputs and
+synchronisations between the replays; every replay must reproduce the eager result bit for bit
+(tallies, counters, profiles, records).  The library clears its outputs and counters with
+kernels, so the graph holds no memset nodes."""
+import pytest
+
+import sputter_inputs as si
+from parity import say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2411_14413_amd as spx  # noqa: E402
+
+
+def _scribble(bufs):
+    for v in bufs.values():
+        if v is not None:
+            v.fill_(255 if v.dtype == torch.uint8 else -7)
+
+
+def test_noalloc_graph_replays_match_eager():
+    cfgs = [si.single_ni(0.5, 20_000), si.single_ni(2.0, 2_000),
+            si.quaternary(0.5, 25.0, 150.0, [3000, 800, 2000, 1200])]
+    plan = spx.Plan(cfgs, si.Params())
+    seed = 21
+    say(f"capture of spx_run_noalloc: {plan.n_particles} particles, {plan.n_segments} segments")
+    ref = plan.allocate(profiles=True, records=True)
+    plan.run_noalloc_into(seed, ref)            # eager (also looks the scratch array up)
+    torch.cuda.synchronize()
+
+    cap = plan.allocate(profiles=True, records=True)
+    other = plan.allocate(profiles=True, records=True)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.run_noalloc_into(seed, cap, stream=s)
+    torch.cuda.synchronize()
+
+    for rep in range(4):
+        _scribble(cap)
+        # eager work of the same plan between the replays: an ordinary run and a no-alloc run
+        # with another seed, which leave their own values in the plan's queue and the scratch
+        plan.run_into(seed + 1 + rep, other)
+        plan.run_noalloc_into(seed + 100 + rep, other)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, v in ref.items():
+            if v is not None:
+                assert torch.equal(v, cap[k]), (rep, k)
+        say(f"  replay {rep}: identical to the eager run")
+
+
+@pytest.mark.parametrize("precision, arrivals", [(32, False), (32, True), (64, False)])
+def test_run_graph_replays_match_eager(precision, arrivals):
+    """spx_run / spx_run_ex inside a capture enqueue their kernels on the capturing stream; the
+    replays of the caller's graph reproduce the eager run."""
+    cfgs = [si.single_ni(0.5, 6_000), si.single_ni(2.0, 600),
+            si.quaternary(0.5, 25.0, 150.0, [900, 300, 600, 400])]
+    plan = spx.Plan(cfgs, si.Params(), precision=precision)
+    seed = 33
+    ref = plan.allocate(profiles=True, records=True, arrivals=arrivals)
+    plan.run_into(seed, ref)
+    torch.cuda.synchronize()
+    cap = plan.allocate(profiles=True, records=True, arrivals=arrivals)
+    other = plan.allocate(profiles=True, records=True, arrivals=arrivals)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.run_into(seed, cap, stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        _scribble(cap)
+        plan.run_into(seed + 1 + rep, other)        # an eager run of the plan between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, v in ref.items():
+            if v is not None:
+                assert torch.equal(v, cap[k]), (precision, arrivals, rep, k)
+    say(f"  spx_run captured (precision {precision}, arrivals {arrivals}): 3 replays identical")
