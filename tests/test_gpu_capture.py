@@ -87,3 +87,30 @@ def test_run_graph_replays_match_eager(precision, arrivals):
             if v is not None:
                 assert torch.equal(v, cap[k]), (precision, arrivals, rep, k)
     say(f"  spx_run captured (precision {precision}, arrivals {arrivals}): 3 replays identical")
+
+
+def test_autotune_refuses_capture():
+    """spx_autotune times and synchronises: inside a capture it returns SPX_ESTATE before any
+    stream work, and the capture around it still records the run that follows."""
+    from paper_2411_14413_amd._native import SPX_ESTATE
+    plan = spx.Plan([si.single_ni(0.5, 4_000)], si.Params())
+    ref = plan.allocate(profiles=True)
+    plan.run_into(5, ref)
+    torch.cuda.synchronize()
+    cap = plan.allocate(profiles=True)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        with pytest.raises(spx.SpxError) as e:
+            plan.autotune(stream=s)
+        plan.run_into(5, cap, stream=s)
+    assert e.value.code == SPX_ESTATE and "capture" in str(e.value)
+    torch.cuda.synchronize()
+    _scribble(cap)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    for k, v in ref.items():
+        if v is not None:
+            assert torch.equal(v, cap[k]), k
