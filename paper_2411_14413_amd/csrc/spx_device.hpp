@@ -793,62 +793,118 @@ __device__ __forceinline__ Term diffusive_resolve(const SegDev<float>& s, Partic
     return Term{HIT_NONE, -1, 0.f};
 }
 
-// Diffusive steps of the thermalised particle of lane L taken with the whole wave: lane j
-// draws step e + 1 + j (Philox block, direction and length), then the wave adds the drawn
-// steps to the offset in order on wave-uniform values, stopping before the first step that
-// leaves the clearance ball or passes the event cap.  The operations are those of
-// diffusive_substep, so the committed position, event and step counts equal those of taking
-// the same steps one at a time.  The step that leaves the ball (the first one when there is
-// no ball) is then held for the surface test, as diffusive_substep holds it; a step past the
-// cap is not taken, and the history, at the cap, escapes.  Every call therefore takes a step,
-// holds one, or leaves the particle at the cap.  Called by the whole wave with L uniform.
-__device__ __forceinline__ void coop_walk(const SegDev<float>& s, uint32_t k0, uint32_t k1, uint32_t cap, uint32_t pid,
-                                          Particle<float>& p, bool& held, int L, int lane)
+// One lane along each 16-lane row (DPP row_shr:1): lane j of a row takes src of lane j - 1; the
+// first lane of a row has no source there and keeps old.
+__device__ __forceinline__ float row_shift1(float old, float src)
 {
-    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.r2), L));
-    const uint32_t pidL = (uint32_t)__builtin_amdgcn_readlane((int)pid, L);
-    const uint32_t e0 = (uint32_t)__builtin_amdgcn_readlane((int)p.e, L);
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), 0x111, 0xF, 0xF, false));
+}
+
+// Diffusive steps of up to four thermalised particles of a wave (its lanes in G) taken with the
+// whole wave.  Each particle gets a span of 64, 32 or 16 lanes (one, two, or three and four
+// particles); lane j of a span draws step e + 1 + j of its particle (Philox block, direction and
+// length).  The offsets the steps reach, T_j = fma(-ell_j, d_j, T_{j-1}) from T_{-1} = xc, are
+// formed along the spans by shifting the chain one lane per round: within 16-lane rows (DPP), one
+// row of every span per phase, the last offset of a row seeding the first lane of the next.  That
+// is the order of diffusive_substep, one step after the other, so each T_j is the value the
+// step-by-step walk computes, and the committed position, event and step counts are equal.  A
+// particle takes its steps up to the first one that leaves the clearance ball or passes the event
+// cap (a phase ends the chain early once every particle has such a step); the step that leaves
+// the ball is held for the surface test, as diffusive_substep holds it, and a step past the cap
+// is not taken (the history, at the cap, escapes).  Every call therefore takes a step, holds one,
+// or leaves each particle at the cap.  Called by the whole wave with G uniform, 1 to 4 lanes.
+__device__ __forceinline__ void coop_walk(uint32_t k0, uint32_t k1, uint32_t cap, uint64_t G, float lam_l2,
+                                          uint32_t cfgcat, uint32_t pid, Particle<float>& p, bool& held, int lane)
+{
+    const int g = __popcll(G);
+    const int sh = g == 1 ? 6 : g == 2 ? 5 : 4;      // log2 of the span
+    const int span = 1 << sh;
+    const int slot = lane >> sh, j = lane & (span - 1);
+    int home[4];                                      // the particles' lanes, in lane order
+    {
+        uint64_t m = G;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            home[q] = m ? __ffsll((unsigned long long)m) - 1 : 0;
+            m &= m - 1;
+        }
+    }
+    const int src = slot == 0 ? home[0] : slot == 1 ? home[1] : slot == 2 ? home[2] : home[3];
+    const uint32_t pidw = (uint32_t)__shfl((int)pid, src);
+    const uint32_t e0 = (uint32_t)__shfl((int)p.e, src);
+    const float r2 = __shfl(p.r2, src);
+    const float lam = __shfl(lam_l2, src);
+    const uint32_t cc = (uint32_t)__shfl((int)cfgcat, src);
     float xc[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) xc[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(p.xc[i]), L));
-    const uint32_t ej = e0 + 1u + (uint32_t)lane;
+    for (int i = 0; i < 3; ++i) xc[i] = __shfl(p.xc[i], src);
+    const uint32_t ej = e0 + 1u + (uint32_t)j;
     uint32_t kc[3];
-    diffusive_codes(diffusive_block(pidL, ej, s.cfgcat, k0, k1), (ej & 1u) != 0, kc);
+    diffusive_codes(diffusive_block(pidw, ej, cc, k0, k1), (ej & 1u) != 0, kc);
     float dir[3];
-    const float ell = diffusive_draw(s.lam_l2, kc, dir);
-    // steps that may be taken at all: within the event cap (the ball test rejects the rest)
-    const uint64_t allowed = __ballot(ej <= cap);
-    int j = 0;
-    for (; j < 64; ++j) {
-        if (!((allowed >> j) & 1ull)) break;
-        float dj[3], t[3];
-        const float ellj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ell), j));
+    const float ell = diffusive_draw(lam, kc, dir);
+    const bool allowed = ej <= cap && slot < g;        // steps within the event cap
+    const float nell = -ell;
+    // t: the lane's offset T_j; u: its input T_{j-1} (at the first lane of a row, the row's seed,
+    // which the shift leaves in place)
+    float t[3], u[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) dj[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dir[i]), j));
-        offset_try(xc, ellj, dj, t);
-        if (!__builtin_amdgcn_readfirstlane((int)offset_holds(t, r2))) break;
+    for (int i = 0; i < 3; ++i) t[i] = u[i] = xc[i];
+    uint64_t ok = 0;
+    const int rows = span >> 4;
+    for (int r = 0; r < rows; ++r) {
 #pragma unroll
-        for (int i = 0; i < 3; ++i) xc[i] = t[i];
+        for (int it = 0; it < 16; ++it) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) u[i] = row_shift1(u[i], t[i]);
+#pragma unroll
+            for (int i = 0; i < 3; ++i) t[i] = __builtin_fmaf(nell, dir[i], u[i]);
+        }
+        // rows 0..r of every span are final: done once each particle has a step it cannot take
+        ok = __ballot(allowed && offset_holds(t, r2));
+        const uint64_t done_rows = r == 3 ? ~0ull : (1ull << (16 * (r + 1))) - 1;
+        bool all = true;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q < g) all = all && (~ok & (done_rows << (q << sh))) != 0;
+        if (all || r == rows - 1) break;
+        float c[3];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) c[i] = __shfl(t[i], lane - 1);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) u[i] = j == 16 * (r + 1) ? c[i] : u[i];
     }
-    // the step that ended the run: held unless it is past the cap (or all 64 were taken)
-    const bool hold = j < 64 && ((allowed >> j) & 1ull);
-    float hd[3] = {0.f, 0.f, 0.f}, hl = 0.f;
-    if (hold) {
-        hl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ell), j));
+    const uint64_t in_cap = __ballot(allowed);
+    const uint64_t span_mask = span == 64 ? ~0ull : (1ull << span) - 1;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) hd[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dir[i]), j));
-    }
-    if (lane == L) {
+    for (int q = 0; q < 4; ++q) {
+        if (q >= g) break;
+        const int b = q << sh;
+        const uint64_t bad = (~ok >> b) & span_mask;
+        const int f = bad ? __ffsll((unsigned long long)bad) - 1 : span;   // steps taken
+        const bool hold = f < span && ((in_cap >> (b + f)) & 1ull);
+        float nx[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) p.xc[i] = xc[i];
-        p.e = e0 + (uint32_t)j;
-        p.ndiff += (uint32_t)j;
+        for (int i = 0; i < 3; ++i)
+            nx[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(f > 0 ? t[i] : xc[i]), f > 0 ? b + f - 1 : b));
+        float hd[3] = {0.f, 0.f, 0.f}, hl = 0.f;
         if (hold) {
+            hl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ell), b + f));
 #pragma unroll
-            for (int i = 0; i < 3; ++i) p.d[i] = hd[i];
-            p.r2 = hl;
-            p.e += 1u;
-            held = true;
+            for (int i = 0; i < 3; ++i) hd[i] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dir[i]), b + f));
+        }
+        if (lane == home[q]) {      // a particle's lane may lie in another particle's span
+#pragma unroll
+            for (int i = 0; i < 3; ++i) p.xc[i] = nx[i];
+            p.e += (uint32_t)f;
+            p.ndiff += (uint32_t)f;
+            if (hold) {
+#pragma unroll
+                for (int i = 0; i < 3; ++i) p.d[i] = hd[i];
+                p.r2 = hl;
+                p.e += 1u;
+                held = true;
+            }
         }
     }
 }

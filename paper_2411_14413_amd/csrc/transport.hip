@@ -504,15 +504,20 @@ __device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<f
             if (T.drained) break;
             continue;
         }
-        // Last walks of a drained wave: each is walked by the whole wave (up to 64 steps per
-        // pass) until its step leaves the ball; then the held steps are tested together.
+        // Last walks of a drained wave: walked by the whole wave, up to four at a time (up to 64,
+        // 32 or 16 steps each per pass), until their steps leave the balls; then the held steps
+        // are tested together.
         // Every pass takes or holds a step of each walker, or leaves it at the cap, where it
         // escapes, so the walks end.
         if (T.drained && __popcll(D) <= COOP_MAX) {
             bool held = false;
-            for (uint64_t W = D; W != 0; W &= W - 1) {
-                const int L = __ffsll((unsigned long long)W) - 1;
-                coop_walk(segs[__builtin_amdgcn_readlane(seg, L)], a.k0, a.k1, a.cap, pid, p, held, L, lane);
+            for (uint64_t W = D; W != 0;) {
+                uint64_t G = 0;                  // the next (up to) four walkers
+                for (int q = 0; q < 4 && W != 0; ++q) {
+                    G |= W & (~W + 1);
+                    W &= W - 1;
+                }
+                coop_walk(a.k0, a.k1, a.cap, G, lam_l2, cfgcat, pid, p, held, lane);
             }
             escape_capped<ARR>(a, bt, segs, seg, pid, p, acc, p.st == ST_DIFFUSIVE && !held && p.e >= a.cap);
             const uint64_t H = __ballot(held);
