@@ -460,11 +460,6 @@ __device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<f
     lds_setup(a, bt, lds);
     const uint64_t total = a.qstate[QS_QUEUE];   // written by the ballistic phase of this round
     const int lane = threadIdx.x & 63;
-    // this wave's REFILL_PREFETCH slots after the block's counters, tally and arrival histograms:
-    // the empty-slot markers (pid words) of the next tickets of its run, loaded straight into LDS
-    uint32_t* const pf = bt.larr + (a.lds_arrivals ? (size_t)a.n_seg * ARR_BINS : 0) +
-                         (size_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) * REFILL_PREFETCH;
-    uint64_t pf_base = 0, pf_n = 0;   // wave-uniform: tickets [pf_base, pf_base + pf_n) are in pf
     Particle<float> p;
     p.st = ST_DEAD;
     p.e = p.ndiff = p.ncoll = 0;
@@ -479,11 +474,7 @@ __device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<f
         const int n_dead = __popcll(dead);
         if (!T.drained && n_dead > 0 && (n_dead >= a.refill_min || n_dead == 64)) {
             const uint64_t my = claim(T, &a.qstate[QS_DIFFUSIVE], TICKET_CHUNK, total, dead, lane);
-            uint32_t qpid = 0xFFFFFFFFu;
-            if (my != ~0ull) {
-                const uint64_t o = my - pf_base;
-                qpid = o < pf_n ? pf[o] : a.queue[my].pid;
-            }
+            const uint32_t qpid = my != ~0ull ? a.queue[my].pid : 0xFFFFFFFFu;
             if (qpid != 0xFFFFFFFFu) {                 // empty slots (left unused by a wave) are skipped
                 const ThermRec r = a.queue[my];
 #pragma unroll
@@ -507,13 +498,6 @@ __device__ __forceinline__ void diffusive_phase(TransportArgs& a, const SegDev<f
                 lam_l2 = __uint_as_float(r.lam_bits);
                 cfgcat = r.cfgcat;
             }
-            // the markers of the run's next tickets, for the next refill: one load per lane that
-            // writes LDS directly (no register held across the walk) and warms the records' lines
-            pf_base = T.tk;
-            pf_n = T.tk_end - T.tk < REFILL_PREFETCH ? T.tk_end - T.tk : REFILL_PREFETCH;
-            if ((uint64_t)lane < pf_n)
-                __builtin_amdgcn_global_load_lds((const void*)&a.queue[pf_base + lane].pid,
-                                                 (__attribute__((address_space(3))) void*)pf, 4, 0, 0);
         }
         const uint64_t D = __ballot(p.st == ST_DIFFUSIVE);
         if (D == 0) {
@@ -714,19 +698,13 @@ size_t transport32_lds(const Plan* P, bool arrivals, bool* lds_counters, bool* l
     return (*lds_counters ? cbytes : 0) + (*lds_tally ? tbytes : 0) + (*lds_arrivals ? abytes : 0);
 }
 
-// Dynamic LDS of the diffusive kernel: the block's share plus each wave's refill prefetch.
-static size_t diffusive_lds(size_t smem, int threads)
-{
-    return smem + (size_t)((threads + 63) / 64) * REFILL_PREFETCH * sizeof(uint32_t);
-}
-
 int occupancy_transport32(const Plan* P, int threads, int* bpc_ballistic, int* bpc_diffusive)
 {
     bool lc, lt, la;
     const size_t smem = transport32_lds(P, false, &lc, &lt, &la);
     int b1 = 0, b2 = 0;
     SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b1, k_ballistic32<false>, threads, smem));
-    SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_diffusive32, threads, diffusive_lds(smem, threads)));
+    SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&b2, k_diffusive32, threads, smem));
     *bpc_ballistic = b1;
     *bpc_diffusive = b2;
     return SPX_OK;
@@ -772,11 +750,10 @@ int build_transport32(Plan* P, uint64_t seed, const Outputs& o, const uint64_t* 
     a.n_bins = (uint32_t)P->n_bins_total;
     bool lc, lt, la;
     const size_t smem = transport32_lds(P, o.arr_E != nullptr, &lc, &lt, &la);
-    const size_t smem_d = diffusive_lds(smem, sh.threads);
     int blocks_diff_arr = sh.blocks_diff;
     if (o.arr_E) {
         int bpc_arr = 0;
-        SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc_arr, k_diffusive32_arr, sh.threads, smem_d));
+        SPX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc_arr, k_diffusive32_arr, sh.threads, smem));
         if (bpc_arr > 0) blocks_diff_arr = std::min(sh.blocks_diff, bpc_arr * P->n_cu);
     }
     a.lds_counters = lc ? 1 : 0;
@@ -818,7 +795,7 @@ int build_transport32(Plan* P, uint64_t seed, const Outputs& o, const uint64_t* 
         dif.func = a.arr_E ? (const void*)k_diffusive32_arr : (const void*)k_diffusive32;
         dif.grid = dim3((unsigned)(a.arr_E ? blocks_diff_arr : sh.blocks_diff));
         dif.block = dim3((unsigned)sh.threads);
-        dif.smem = (uint32_t)smem_d;
+        dif.smem = (uint32_t)smem;
         dif.phase = 2;
         dif.arg(a);
         dif.arg(segs);
