@@ -341,7 +341,7 @@ def main():
                     help="run one device copy of this size first (HBM counter calibration under rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the tally reduce across GPUs "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the tally reduce across GPUs "
               "is designed but not built); use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
