@@ -119,7 +119,7 @@ constexpr uint64_t QUEUE_SLACK_WAVES = 8192;  // waves that may leave slots unus
 constexpr size_t LDS_COUNTERS_MAX = 16384;   // bytes: up to 256 segments
 constexpr int RT_MAX_NODES = 256;             // nodes of a measured racetrack profile
 constexpr int OBJ_MAX_SEG = 32;               // absorbing objects of one (config, cathode) run
-constexpr uint64_t TICKET_CHUNK = 64;        // queued atoms a diffusive wave claims per global atomic
+constexpr uint64_t TICKET_CHUNK = 128;       // queued atoms a diffusive wave claims per global atomic
 // launch tickets a ballistic wave claims per global atomic, at most: ballistic histories are
 // short, so their waves come back for tickets often and small chunks queue them on the one
 // counter; the chunk of a round is also kept small enough for every wave to take several
