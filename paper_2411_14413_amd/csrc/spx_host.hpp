@@ -111,6 +111,9 @@ struct Outputs {
 
 constexpr uint64_t ROUND_MAX = 1ull << 28;   // tickets per round: a 12.9 GB queue of thermalised atoms
 constexpr uint64_t QUEUE_CHUNK = 64;         // queue slots a wave reserves per atomic
+// exactly one lane per slot: a hand-over of up to 64 atoms continues into at most one fresh
+// run, and a wave marks its unused reserved slots one per lane
+static_assert(QUEUE_CHUNK == 64, "queue runs hold one slot per lane of a wave");
 // The round's three counters (ballistic tickets, queue length, diffusive tickets) sit 256 bytes
 // apart: every wave's claims and queue reservations are atomics on them, and on one cache line
 // the two kinds of atomics of the ballistic phase would queue behind each other.
