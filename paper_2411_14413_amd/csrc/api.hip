@@ -894,8 +894,8 @@ static int autotune(Plan* P, hipStream_t st)
     int bb = P->blocks, bd = P->blocks_diff, bt = P->threads, br = P->refill_min, bm = P->refill_ballistic;
     int bdef = DEFER_MIN;
     const int thread_opts[] = {256, 512, 1024};
-    // (refill_min, refill_ballistic): three runs measure three values of each threshold
-    const int mode_opts[][2] = {{4, 16}, {8, 24}, {16, 8}};
+    // (refill_min, refill_ballistic): four runs measure four values of each threshold
+    const int mode_opts[][2] = {{2, 12}, {4, 16}, {8, 24}, {16, 8}};
     for (int t : thread_opts) {
         if (rc != SPX_OK) break;
         int bpc = 0, bpc_d = 0;
