@@ -934,6 +934,12 @@ static int autotune(Plan* P, hipStream_t st)
         best_d = ms.d;
         bdef = defer;
     }
+    // where doubling did not help, half of it: fewer held steps per test pass pays off where
+    // walks are short and a held lane would otherwise idle longer
+    if (rc == SPX_OK && bdef == DEFER_MIN) {
+        const PhaseMs ms = time_shape(bb, bd, bt, br, bm, DEFER_MIN / 2);
+        if (rc == SPX_OK && ms.d < best_d) bdef = DEFER_MIN / 2;
+    }
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
     (void)hipFree(d_tf);
