@@ -130,7 +130,7 @@ constexpr uint64_t TICKET_CHUNK_BALLISTIC_MAX = 512;
 constexpr int DEFER_MIN = 8;                  // default: held diffusive steps that trigger a wave's surface tests
 // advances (two diffusive steps each) a wave takes between its checks for held steps, dead
 // lanes and the end of the walk; the checks (ballots, branches) then cost little per step
-constexpr int ADVANCES_PER_CHECK = 6;
+constexpr int ADVANCES_PER_CHECK = 7;
 constexpr int COOP_MAX = 8;                   // drained waves with at most this many live lanes walk cooperatively
 constexpr size_t LDS_TALLY_MAX = 49152;      // bytes: up to 12288 bins
 constexpr size_t LDS_ARRIVALS_MAX = 4096;     // bytes: arrival histograms of up to 6 segments
